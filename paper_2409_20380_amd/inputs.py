@@ -1,0 +1,238 @@
+"""Seeded synthetic inputs shared by the tests, the bench and the oracle runs.
+
+This module only *generates problem data*: a layered box discretised by
+second-order (10-node) tetrahedra, its material table, the fixed-bottom mask,
+a partition of the nodes into predictor regions, and a band-limited random
+base-acceleration record.  It holds none of the method's arithmetic (no
+element integrals, no solver, no predictor): the oracle under ``oracle/`` and
+the HIP library each compute everything else on their own.
+
+Workload shapes follow the paper's application (Sec. 3.1): a horizontally
+stratified elastic ground model (soft layer over stiffer layer), meshed with
+quadratic tetrahedra, with the bottom fixed, driven by random waves.  The
+paper's own ground models and impulse inputs are not available, so these
+synthetic stand-ins are used instead.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+# Local node order of a 10-node tetrahedron used throughout the project:
+# the four vertices, then the edge midpoints of edges (0,1),(1,2),(0,2),(0,3),(1,3),(2,3).
+TET10_EDGES = ((0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3))
+
+
+# --------------------------------------------------------------------------
+# Mesh
+# --------------------------------------------------------------------------
+def _kuhn_tets():
+    """Six tetrahedra of the Kuhn (Freudenthal) split of the unit cube.
+
+    Every tet runs from corner (0,0,0) to corner (1,1,1) along a monotone path
+    of unit steps; the split is the same in every cell, so the mesh conforms.
+    Vertices are returned as integer corner offsets, reordered so that each
+    tet has positive orientation.
+    """
+    tets = []
+    for perm in ((0, 1, 2), (1, 2, 0), (2, 0, 1), (0, 2, 1), (2, 1, 0), (1, 0, 2)):
+        v0 = np.zeros(3, dtype=np.int64)
+        v1 = v0.copy(); v1[perm[0]] = 1
+        v2 = v1.copy(); v2[perm[1]] = 1
+        v3 = np.ones(3, dtype=np.int64)
+        verts = [v0, v1, v2, v3]
+        det = np.linalg.det(np.stack([v1 - v0, v2 - v0, v3 - v0]).astype(float))
+        if det < 0:
+            verts = [v0, v2, v1, v3]
+        tets.append(verts)
+    return tets
+
+
+@dataclasses.dataclass
+class BoxMesh:
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    coords: np.ndarray      # [N,3] float64, metres; z is up, z=0 is the bottom
+    conn: np.ndarray        # [E,10] int32, vertex ids then edge-midpoint ids
+    lattice: np.ndarray     # [N,3] int64 index of each node on the half-cell lattice
+
+    @property
+    def n_nodes(self) -> int:
+        return self.coords.shape[0]
+
+    @property
+    def n_elems(self) -> int:
+        return self.conn.shape[0]
+
+
+def box_mesh(nx: int, ny: int, nz: int, h: float = 2.5) -> BoxMesh:
+    """nx*ny*nz cubic cells of edge h, each split into 6 straight 10-node tets.
+
+    Nodes sit on the half-cell lattice, (2nx+1)(2ny+1)(2nz+1) of them, numbered
+    x fastest, then y, then z.  Element vertices are cell corners; edge nodes
+    are the lattice points halfway along each edge.
+    """
+    Lx, Ly, Lz = 2 * nx + 1, 2 * ny + 1, 2 * nz + 1
+    ii, jj, kk = np.meshgrid(np.arange(Lx), np.arange(Ly), np.arange(Lz), indexing="ij")
+    lat = np.stack([ii.ravel(order="F"), jj.ravel(order="F"), kk.ravel(order="F")], axis=1)
+    # order: x fastest -> use Fortran ravel of an (x,y,z) grid
+    node_id = lambda p: p[..., 0] + Lx * (p[..., 1] + Ly * p[..., 2])  # noqa: E731
+    order = np.argsort(node_id(lat), kind="stable")
+    lat = lat[order]
+    coords = lat.astype(np.float64) * (h / 2.0)
+
+    cx, cy, cz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    cells = np.stack([cx.ravel(order="F"), cy.ravel(order="F"), cz.ravel(order="F")], axis=1)
+    cell_key = cells[:, 0] + nx * (cells[:, 1] + ny * cells[:, 2])
+    cells = cells[np.argsort(cell_key, kind="stable")]
+
+    tets = _kuhn_tets()
+    conn = np.empty((cells.shape[0], 6, 10), dtype=np.int64)
+    for t, verts in enumerate(tets):
+        vlat = [2 * cells + 2 * v[None, :] for v in verts]      # vertex lattice coords
+        ids = [node_id(v) for v in vlat]
+        for m, (a, b) in enumerate(TET10_EDGES):
+            ids.append(node_id((vlat[a] + vlat[b]) // 2))
+        conn[:, t, :] = np.stack(ids, axis=1)
+    conn = conn.reshape(-1, 10).astype(np.int32)
+    return BoxMesh(nx, ny, nz, h, coords, conn, lat)
+
+
+# --------------------------------------------------------------------------
+# Materials, boundary, regions
+# --------------------------------------------------------------------------
+@dataclasses.dataclass
+class Layer:
+    vs: float
+    rho: float
+    vp_over_vs: float = 1.9
+
+    def row(self):
+        return (self.rho, self.vp_over_vs * self.vs, self.vs)
+
+
+DEFAULT_LAYERS = (Layer(vs=400.0, rho=2000.0), Layer(vs=200.0, rho=1800.0))  # bottom, top
+
+
+def two_layer_materials(mesh: BoxMesh, layers=DEFAULT_LAYERS):
+    """Material id per element by centroid depth: lower half of the box gets
+    layers[0] (bedrock-like), upper half layers[1] (sediment-like).
+
+    Returns (elem_mat int32 [E], mat float64 [n_mat,3] with columns rho, vp, vs).
+    """
+    zc = mesh.coords[mesh.conn[:, :4], 2].mean(axis=1)
+    z_split = 0.5 * mesh.nz * mesh.h
+    elem_mat = (zc > z_split).astype(np.int32)
+    mat = np.array([ly.row() for ly in layers], dtype=np.float64)
+    return elem_mat, mat
+
+
+def fixed_bottom(mesh: BoxMesh) -> np.ndarray:
+    """uint8 [N,3]: 1 where the displacement component is fixed (z = 0 face)."""
+    fixed = np.zeros((mesh.n_nodes, 3), dtype=np.uint8)
+    fixed[mesh.lattice[:, 2] == 0, :] = 1
+    return fixed
+
+
+def _split(n: int, b: int):
+    """Block boundaries of [0,n) in chunks of b, the remainder merged into the last."""
+    nb = max(1, n // b)
+    edges = [i * b for i in range(nb)] + [n]
+    return np.asarray(edges)
+
+
+def block_regions(mesh: BoxMesh, block: int = 8) -> np.ndarray:
+    """Predictor regions: blocks of block^3 lattice nodes (512 for block=8).
+
+    Returns int32 [N] region id per node; a short remainder along an axis is
+    merged into the last block so no region is thin.
+    """
+    out = np.empty(mesh.n_nodes, dtype=np.int64)
+    Ls = [2 * mesh.nx + 1, 2 * mesh.ny + 1, 2 * mesh.nz + 1]
+    ids = []
+    for d in range(3):
+        e = _split(Ls[d], block)
+        ids.append(np.searchsorted(e, mesh.lattice[:, d], side="right") - 1)
+    nb = [len(_split(L, block)) - 1 for L in Ls]
+    out[:] = ids[0] + nb[0] * (ids[1] + nb[1] * ids[2])
+    return out.astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# Input wave
+# --------------------------------------------------------------------------
+def base_wave(seed: int, nt: int, dt: float, f_lo: float = 0.1, f_hi: float = 2.5,
+              ng: int = 8192, ramp_s: float = 0.2) -> np.ndarray:
+    """Seeded band-limited Gaussian base acceleration, shape [nt+1, 3] (m/s^2).
+
+    For each component k: ng standard normals from default_rng([seed, k]),
+    zero every Fourier bin outside [f_lo, f_hi] Hz, scale to unit RMS, take the
+    first nt+1 samples (t = 0, dt, ...), and taper the first ramp_s seconds
+    with sin^2 so the record starts from rest (g(0) = 0).
+    """
+    n = max(ng, nt + 1)
+    out = np.empty((nt + 1, 3), dtype=np.float64)
+    freqs = np.fft.rfftfreq(n, d=dt)
+    band = (freqs >= f_lo) & (freqs <= f_hi)
+    t = np.arange(nt + 1) * dt
+    ramp = np.where(t < ramp_s, np.sin(0.5 * np.pi * np.clip(t / ramp_s, 0, 1)) ** 2, 1.0)
+    for k in range(3):
+        rng = np.random.default_rng([seed, k])
+        w = rng.standard_normal(n)
+        W = np.fft.rfft(w)
+        W[~band] = 0.0
+        g = np.fft.irfft(W, n=n)
+        g /= math.sqrt(np.mean(g * g))
+        out[:, k] = g[: nt + 1] * ramp
+    return out
+
+
+def random_vector(seed: int, n: int) -> np.ndarray:
+    """Seeded standard-normal float64 vector (parity-test operand)."""
+    return np.random.default_rng([seed, 7919]).standard_normal(n)
+
+
+# --------------------------------------------------------------------------
+# Workloads
+# --------------------------------------------------------------------------
+def rayleigh_coefficients(zeta: float, f1: float, f2: float):
+    """Mass/stiffness-proportional damping giving ratio zeta at f1 and f2 (Hz)."""
+    w1, w2 = 2 * math.pi * f1, 2 * math.pi * f2
+    return 2 * zeta * w1 * w2 / (w1 + w2), 2 * zeta / (w1 + w2)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    cells: tuple
+    h: float = 2.5
+    dt: float = 0.01
+    nt: int = 100
+    s: int = 16
+    tol: float = 1e-8
+    seed: int = 0
+    zeta: float = 0.05
+    f_band: tuple = (0.1, 2.5)
+    region_block: int = 8
+
+    @property
+    def rayleigh(self):
+        return rayleigh_coefficients(self.zeta, *self.f_band)
+
+    def build(self):
+        """Mesh, materials, mask, regions and wave for this workload."""
+        mesh = box_mesh(*self.cells, h=self.h)
+        elem_mat, mat = two_layer_materials(mesh)
+        fixed = fixed_bottom(mesh)
+        regions = block_regions(mesh, self.region_block)
+        wave = base_wave(self.seed, self.nt, self.dt, *self.f_band)
+        return mesh, elem_mat, mat, fixed, regions, wave
+
+
+# The small case the oracle finishes in seconds, and the single-GPU headline case.
+SMALL = Workload("box8x8x8_p2tet_fp64", cells=(8, 8, 8), nt=100, s=16)
+PLAIN = Workload("box64x64x32_p2tet_fp64", cells=(64, 64, 32), nt=1000, s=32)

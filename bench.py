@@ -1,0 +1,188 @@
+#!/usr/bin/env python
+"""Throughput of the plain FP64 method on one MI355X.
+
+Workload: layered elastic box of 64 x 64 x 32 cubic cells (2.5 m), each cell
+split into 6 straight 10-node tetrahedra: 1,081,665 nodes, 3,244,995 dof,
+786,432 elements; Newmark-beta (beta = 1/4, gamma = 1/2), dt = 0.01 s,
+Rayleigh damping 5 % at 0.1 and 2.5 Hz; bottom fixed; seeded band-limited
+base acceleration (0.1 - 2.5 Hz); initial guess = Adams-Bashforth 4 plus the
+regional snapshot predictor over the last 32 steps (regions of 8^3 lattice
+nodes); 3x3 block-Jacobi PCG to relative residual 1e-8.
+
+One bench step = one full time step (right-hand side, predictor, PCG refine,
+Newmark update) on inputs resident in HBM.  Prints ONE JSON line on stdout;
+progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def ebe_pcg_bytes_per_element(n_nodes: int, n_elems: int) -> float:
+    """Algorithmic HBM bytes of one fused PCG matvec launch, per element.
+
+    Matvec (Eq. EBE) compulsory traffic: connectivity 10 x 4 B + material 4 B
+    per element, and per node coordinates, p read and q written (3 x 24 B);
+    the fused direction update p = z + beta p_prev adds z read and the new p
+    written (2 x 24 B per node).  Node terms are spread over n_nodes/n_elems.
+    """
+    per_node = 5 * 24.0
+    return 44.0 + per_node * n_nodes / n_elems
+
+
+def cpu_baseline(wl, mesh, em, mat, fx, regions, wave, steps):
+    """The CPU oracle (BCSR block-Jacobi PCG + the same predictor) timed on host cores."""
+    import numpy as np
+
+    import oracle
+    aR, bR = wl.rayleigh
+    t0 = time.time()
+    model = oracle.Model(mesh.coords, mesh.conn, em, mat, fx, 4 / wl.dt ** 2 + 2 * aR / wl.dt,
+                         1 + 2 * bR / wl.dt)
+    t_asm = time.time() - t0
+    log(f"oracle assembled in {t_asm:.1f} s")
+    st = oracle.Stepper(model, wl.dt, aR, bR, s=wl.s, kind=2, tol=wl.tol, regions=regions)
+    iters = []
+    t0 = time.time()
+    for it in range(1, steps + 1):
+        rec, _, _ = st.step(g=wave[it])
+        iters.append(rec.iters)
+    dt = time.time() - t0
+    dof = 3 * mesh.n_nodes
+    return {
+        "value": dof * steps / dt,
+        "unit": "DOF*steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"steps 1-{steps} of the same workload from rest ({np.mean(iters):.0f} PCG iterations/step; "
+                   f"BCSR assembly of {t_asm:.0f} s excluded); {dt:.1f} s wall"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=250, help="timed time steps")
+    ap.add_argument("--warmup", type=int, default=250, help="untimed time steps before the timed ones")
+    ap.add_argument("--timing-every", type=int, default=8, help="bracket every n-th matvec launch with events")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.json"))
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): this build has no "
+              "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2409_20380_amd import ebe, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    wl = inputs.PLAIN
+    nt = args.warmup + args.steps
+    wl_run = inputs.Workload(wl.name, cells=wl.cells, h=wl.h, dt=wl.dt, nt=nt, s=wl.s, tol=wl.tol,
+                             seed=wl.seed, region_block=wl.region_block)
+    mesh, em, mat, fx, regions, wave = wl_run.build()
+    dof = 3 * mesh.n_nodes
+    log(f"mesh {wl.cells}: {mesh.n_nodes} nodes, {dof} dof, {mesh.n_elems} elements")
+    aR, bR = wl.rayleigh
+    sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol)
+    t0 = time.time()
+    sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
+    sizes = sol.sizes()
+    log(f"assembled in {time.time() - t0:.1f} s: {sizes}")
+
+    for it in range(1, args.warmup + 1):
+        st = sol.step(base_acc=wave[it])
+        if it % 50 == 0 or it == args.warmup:
+            log(f"warmup step {it}: {st.iters} iters, res_true {st.res_true:.2e}")
+
+    sol.set_kernel_timing(args.timing_every)
+    iters, res = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(args.warmup + 1, nt + 1):
+        st = sol.step(base_acc=wave[it])
+        iters.append(st.iters)
+        res.append(st.res_true)
+        if st.status != 0:
+            raise RuntimeError(f"step {it} did not converge")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n_timed, ebe_ms = sol.kernel_time()
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; mean iters {np.mean(iters):.1f}; "
+        f"matvec {ebe_ms * 1e3:.1f} us over {n_timed} timed launches")
+
+    bpe = ebe_pcg_bytes_per_element(mesh.n_nodes, mesh.n_elems)
+    launch_bytes = bpe * mesh.n_elems
+    achieved = launch_bytes / (ebe_ms * 1e-3) / 1e9 if ebe_ms > 0 else 0.0
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        if tj.get("workload") == wl.name and tj.get("kernel_source_sha") == kernel_source_sha():
+            traffic = tj.get("bytes_per_launch")
+
+    out = {
+        "metric": "DOF*steps/s at rel. residual 1e-8",
+        "value": dof * args.steps / elapsed,
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": list(wl.cells), "nodes": mesh.n_nodes, "dof": dof,
+                   "elements": mesh.n_elems, "dt": wl.dt, "snapshots": wl.s, "tol": wl.tol,
+                   "predictor": "AB4 + regional snapshot map", "timed_steps": f"{args.warmup + 1}-{nt}"},
+        "cg_iters_per_step": float(np.mean(iters)),
+        "cg_iters_min_max": [int(np.min(iters)), int(np.max(iters))],
+        "max_true_rel_residual": float(np.max(res)),
+        "ebe_matvec_hbm_gbs": achieved,
+        "roofline": {"kernel": "k_ebe<PCG> (fused direction update + EBE matvec + (p,Ap))",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": launch_bytes, "mean_launch_ms": ebe_ms, "timed_launches": n_timed},
+    }
+    sol.close()
+    if not args.no_cpu_baseline:
+        log(f"CPU baseline: oracle, {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(wl_run, mesh, em, mat, fx, regions, wave, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def kernel_source_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2409_20380_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

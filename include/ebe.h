@@ -1,0 +1,210 @@
+/*
+ * ebe.h -- C ABI of the MI355X (gfx950) library for repeated implicit time
+ * stepping with a data-driven initial guess refined by block-Jacobi PCG.
+ *
+ * Method: Ichimura et al., "Heterogeneous computing in a strongly-connected
+ * CPU-GPU environment: fast multiple time-evolution equation-based modeling
+ * accelerated using data-driven approach", arXiv:2409.20380.
+ *   - problem statement: solve A x^it = f^it for it = 1..nt in sequence
+ *     (Sec. 2.1, Eq. general);
+ *   - application: linear elastodynamics discretised with straight 10-node
+ *     tetrahedra and Newmark-beta with damping (Sec. 3.1, Eq. GE:DIS and
+ *     Eq. timestep);
+ *   - matvec: matrix-free element-by-element product (Sec. 2.2 Eq. EBE,
+ *     Sec. 3.2 Eq. eqebefem);
+ *   - solver: conjugate gradient with a 3x3 block-Jacobi preconditioner
+ *     (Sec. 3.2, Algorithm 1), stopped when ||r||/||f|| < tol;
+ *   - predictor: x-bar = predictor(X, F, f) (Sec. 2.2, Eq. predictor), made
+ *     concrete as an Adams-Bashforth 4-step estimate plus a regional
+ *     least-squares map over the Adams-Bashforth errors of the past s steps
+ *     (Sec. 3.2).
+ *
+ * Conventions
+ *   - Every call returns an int status: EBE_OK (0), EBE_NOT_CONVERGED (1,
+ *     results and statistics are still written) or a negative error code.
+ *     The message of the last error is returned by ebe_last_error().
+ *     No C++ exception crosses this boundary.
+ *   - Host pointers appear only in ebe_assemble, ebe_get_regions and the
+ *     3-value base acceleration; they are read during the call and may be
+ *     freed afterwards.
+ *   - All other vectors are caller-owned DEVICE pointers on the handle's
+ *     device: contiguous float64 arrays of length 3*n_nodes, node-major with
+ *     the x, y, z components interleaved (dof = 3*node + component), in the
+ *     caller's node numbering.  They are borrowed for the duration of the
+ *     call only.  The library permutes them into its own internal order.
+ *   - The library owns all of its internal buffers and frees them in
+ *     ebe_destroy.  All work is ordered on the stream given to ebe_create.
+ *     Calls that fill a statistics struct synchronise that stream before
+ *     returning.  A handle is not thread-safe.
+ *   - Degrees of freedom flagged as fixed carry zero displacement; the
+ *     operator A has identity rows and columns there (A_bc = Z A Z + I - Z,
+ *     Z the free-dof mask), and every right-hand side is zeroed there.
+ */
+#ifndef EBE_H
+#define EBE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBE_OK 0
+#define EBE_NOT_CONVERGED 1
+#define EBE_E_INVALID_ARG (-1)
+#define EBE_E_HIP (-2)
+#define EBE_E_NO_MEMORY (-3)
+#define EBE_E_BAD_STATE (-4)
+#define EBE_E_NONFINITE (-5)
+
+/* Kinds of initial guess for the next step's increment. */
+#define EBE_PRED_ZERO 0      /* x-bar = 0 */
+#define EBE_PRED_AB4 1       /* Adams-Bashforth 4-step estimate (Sec. 3.2) */
+#define EBE_PRED_SNAPSHOT 2  /* AB4 + regional snapshot map (Sec. 3.2) */
+
+typedef struct ebe_handle ebe_handle;
+
+typedef struct {
+    double dt;              /* time increment (s) */
+    double rayleigh_alpha;  /* damping C = alpha M + beta K (1/s) */
+    double rayleigh_beta;   /* (s) */
+    double tol;             /* relative residual tolerance of Algorithm 1 (e.g. 1e-8) */
+    double drop_tol;        /* snapshot column kept only if its part orthogonal to the
+                               earlier kept columns has norm >= drop_tol * its norm
+                               (<= 0: 1e-6) */
+    int32_t max_iter;       /* PCG iteration cap per solve (<= 0: 10000) */
+    int32_t s;              /* snapshot window: number of input columns, 0..32 */
+    int32_t predictor;      /* EBE_PRED_* */
+    int32_t region_nodes;   /* nodes per predictor region when ebe_assemble receives no
+                               region map (<= 0: 512) */
+    int32_t patch_elems;    /* elements per EBE patch, 1..64 (<= 0: 64) */
+    int32_t chunk_iters;    /* PCG iterations enqueued between convergence checks
+                               (<= 0: adaptive) */
+    int32_t reserved[6];
+} ebe_config;
+
+typedef struct {
+    int32_t iters;      /* PCG loop trips (q = A p products), the r0 product excluded */
+    int32_t restarts;   /* restarts after a true-residual check failed */
+    int32_t status;     /* EBE_OK or EBE_NOT_CONVERGED */
+    int32_t pad;
+    double res0;        /* ||b - A x-bar|| / ||b|| */
+    double res_rec;     /* recursive residual at exit, relative */
+    double res_true;    /* ||b - A x|| / ||b|| recomputed at exit */
+    double bnorm;       /* ||b|| */
+} ebe_solve_stats;
+
+typedef struct {
+    int32_t it;         /* index of the step just completed (1-based) */
+    int32_t s_eff;      /* snapshot columns used, min(s, it - 2), 0 if none */
+    int32_t iters;
+    int32_t restarts;
+    int32_t status;
+    int32_t pad;
+    double res0, res_rec, res_true, bnorm;
+} ebe_step_stats;
+
+/* Version string of the library. */
+const char* ebe_version(void);
+
+/* Create a handle on the current HIP device.  stream: a hipStream_t (may be
+ * NULL for the default stream), e.g. torch.cuda.current_stream().cuda_stream.
+ * Errors: INVALID_ARG (bad config), HIP. */
+int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out);
+
+/* Free every device and host resource of the handle.  NULL is accepted. */
+int ebe_destroy(ebe_handle* h);
+
+/* Message of the last error on this handle (or of the last failed create when
+ * h is NULL).  Owned by the library, valid until the next call. */
+const char* ebe_last_error(const ebe_handle* h);
+
+/* Mesh and material data (Sec. 3.1): straight 10-node tetrahedra.
+ *   coords  host [n_nodes][3]  node coordinates (m)
+ *   conn    host [n_elems][10] node ids: 4 vertices, then the midpoints of
+ *           edges (0,1),(1,2),(0,2),(0,3),(1,3),(2,3); positive orientation
+ *           det[x1-x0, x2-x0, x3-x0] > 0; edge nodes must sit at the edge
+ *           midpoints (geometry is taken from the vertices)
+ *   elem_mat host [n_elems] material id in [0, n_mat)
+ *   mat     host [n_mat][3] density rho, P velocity vp, S velocity vs;
+ *           mu = rho vs^2, lambda = rho (vp^2 - 2 vs^2)
+ *   fixed   host [n_nodes][3] 1 = component fixed (zero displacement)
+ *   region_of_node host [n_nodes] predictor region id in [0, R), or NULL to
+ *           let the library group nodes into spatially compact regions of
+ *           cfg.region_nodes nodes (query them with ebe_get_regions)
+ * Builds the element patches, the internal node order, the element
+ * geometry checks and the block-Jacobi inverse, and resets the state to rest
+ * (u = v = a = 0, empty history, step 0).
+ * Errors: INVALID_ARG (ids out of range, inverted or degenerate element,
+ * misplaced edge node, node used both as vertex and edge node), NO_MEMORY, HIP. */
+int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n_elems,
+                 const int32_t* conn, const int32_t* elem_mat, int32_t n_mat, const double* mat,
+                 const uint8_t* fixed, const int32_t* region_of_node);
+
+/* Region id of every node (host [n_nodes]); returns the region count in *n_regions. */
+int ebe_get_regions(ebe_handle* h, int32_t* region_of_node, int32_t* n_regions);
+
+/* q = A_bc p with A = (4/dt^2 + 2 alpha/dt) M + (1 + 2 beta/dt) K (the Newmark
+ * system matrix of Eq. GE:DIS with Rayleigh damping), evaluated element by
+ * element (Eq. EBE) without storing any matrix. */
+int ebe_apply(ebe_handle* h, const double* p, double* q);
+
+/* q = cm * M p + ck * K p, unconstrained (no fixed-dof handling). */
+int ebe_apply_mk(ebe_handle* h, double cm, double ck, const double* p, double* q);
+
+/* z = B^{-1} r, B the 3x3 diagonal blocks of A_bc (Algorithm 1 preconditioner). */
+int ebe_precond(ebe_handle* h, const double* r, double* z);
+
+/* Right-hand side of the next step for the increment du = u^it - u^(it-1):
+ *   b = f + C v + M (a + (4/dt) v) - K u,  zero on fixed dofs,
+ * from the current state (u, v, a), where f = f_ext (device, may be NULL)
+ * minus sum_k base_acc[k] M r_k (host [3], may be NULL; r_k the rigid unit
+ * translation along axis k: the inertial load of a uniform base acceleration). */
+int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* b);
+
+/* Initial guess of the next step's increment from the stored history
+ * (Eq. predictor with the concrete predictor of Sec. 3.2 chosen by
+ * cfg.predictor).  f_next is accepted for interface completeness and unused
+ * by the built-in predictors.  *s_eff receives the snapshot columns used
+ * (may be NULL).  The state is not modified. */
+int ebe_predict(ebe_handle* h, const double* f_next, double* dxbar, int32_t* s_eff);
+
+/* Algorithm 1: solve A_bc x = b to ||b - A x|| / ||b|| < tol starting from the
+ * guess in x (overwritten with the solution).  If ||b|| = 0, x = 0 with zero
+ * iterations.  Returns NOT_CONVERGED when max_iter is reached, NONFINITE if a
+ * scalar of the iteration is not finite. */
+int ebe_refine(ebe_handle* h, const double* b, double* x, ebe_solve_stats* stats);
+
+/* One time step: right-hand side, predictor, Algorithm 1, Newmark-beta
+ * (beta = 1/4, gamma = 1/2) update of u, v, a, velocity history and snapshot
+ * ring.  f_ext (device) and base_acc (host [3]) as in ebe_rhs, at the new time.
+ * stats may be NULL (then the call does not synchronise). */
+int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_step_stats* stats);
+
+/* Checkpoint / resume.  u, v, a: device [3N] each, caller order.
+ * History: vhist device [4][3N] = v^it, v^(it-1), v^(it-2), v^(it-3);
+ * ring device [s+1][3N] with e^j = du^j - du_AB^j in slot (j-1) mod (s+1);
+ * it = completed steps. */
+int ebe_get_state(ebe_handle* h, double* u, double* v, double* a);
+int ebe_set_state(ebe_handle* h, const double* u, const double* v, const double* a);
+int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it);
+int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it);
+
+/* Block until all work enqueued on the handle's stream is done. */
+int ebe_sync(ebe_handle* h);
+
+/* Kernel timing: when enabled, every n-th launch of the element-by-element
+ * PCG matvec kernel is bracketed by HIP events on the handle's stream.
+ * ebe_kernel_time returns the number of timed launches and their mean
+ * duration in milliseconds since the last reset. */
+int ebe_set_kernel_timing(ebe_handle* h, int32_t every_n);
+int ebe_kernel_time(ebe_handle* h, int64_t* launches, double* mean_ms);
+
+/* Sizes used for roofline accounting of one PCG iteration: n_nodes, n_elems,
+ * n_patch_nodes (sum over patches of the nodes each patch touches), patches. */
+int ebe_sizes(ebe_handle* h, int64_t* n_nodes, int64_t* n_elems, int64_t* n_patch_nodes, int64_t* n_patches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBE_H */

@@ -1,0 +1,664 @@
+// api.hip -- C ABI of the library (declared in include/ebe.h): handle
+// management, assembly and the per-step orchestration
+//   right-hand side -> Adams-Bashforth 4 -> regional snapshot map ->
+//   Algorithm 1 (block-Jacobi PCG, element-by-element matvec) -> Newmark.
+// Every numerical step runs in the kernels of kernels.hip; this file only
+// allocates, copies topology to the device and enqueues work on the stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ebe.h"
+#include "kernels.h"
+#include "topology.h"
+
+using namespace ebe;
+
+namespace {
+
+struct HipError {
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess) throw HipError{std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+
+struct Arg {
+    std::string msg;
+};
+struct State {
+    std::string msg;
+};
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct ebe_handle {
+    ebe_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    bool assembled = false;
+    double cM = 0, cK = 0;
+    Topology T;
+    DevPatches dp{};
+    DevNodes dn{};
+    std::vector<void*> allocs;
+    int32_t* d_i2u = nullptr;
+    int32_t* d_u2i = nullptr;
+    int32_t* d_region_start = nullptr;
+    double* binv6 = nullptr;
+    double* qbuf = nullptr;
+    // state (internal node order)
+    double* u = nullptr;
+    double* a = nullptr;
+    double* vh[4] = {nullptr, nullptr, nullptr, nullptr};
+    int head = 0;  // vh[(head + j) & 3] = v^(it - j)
+    double* ring = nullptr;
+    int32_t it = 0;
+    // scratch
+    double *dab = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr};
+    double *t0 = nullptr, *t1 = nullptr, *coef = nullptr;
+    int par = 0;
+    int last_iters = 0;
+    DevScalars* sc = nullptr;
+    DevScalars* sc_host = nullptr;
+    double* partial_pap = nullptr;
+    double* partial_upd = nullptr;
+    unsigned* counters = nullptr;
+    // kernel timing
+    int timing_every = 0;
+    int64_t pcg_launches = 0;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    double time_sum_ms = 0.0;
+    int64_t time_n = 0;
+
+    int64_t n3() const { return 3 * T.n_nodes; }
+    double* ring_slot(int k) const { return ring + (int64_t)k * n3(); }
+    double* vslot(int j) const { return vh[(head + j) & 3]; }
+
+    template <class X>
+    X* alloc(size_t count) {
+        void* p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(X));
+        if (e != hipSuccess) throw std::bad_alloc();
+        allocs.push_back(p);
+        return static_cast<X*>(p);
+    }
+    template <class X>
+    X* upload(const std::vector<X>& v) {
+        X* d = alloc<X>(v.size());
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, stream));
+        return d;
+    }
+    void free_all() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* p : allocs) (void)hipFree(p);
+        allocs.clear();
+        for (auto& pr : ev_pending) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        ev_pending.clear();
+        for (auto e : ev_free) (void)hipEventDestroy(e);
+        ev_free.clear();
+        assembled = false;
+    }
+};
+
+namespace {
+
+template <class F>
+int guarded(ebe_handle* h, F&& f) {
+    if (!h) return EBE_E_INVALID_ARG;
+    h->err.clear();
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        return f();
+    } catch (const Arg& e) {
+        h->err = e.msg;
+        return EBE_E_INVALID_ARG;
+    } catch (const State& e) {
+        h->err = e.msg;
+        return EBE_E_BAD_STATE;
+    } catch (const HipError& e) {
+        h->err = e.msg;
+        return EBE_E_HIP;
+    } catch (const std::bad_alloc&) {
+        h->err = "out of memory";
+        return EBE_E_NO_MEMORY;
+    } catch (const std::exception& e) {
+        h->err = e.what();
+        return EBE_E_HIP;
+    } catch (...) {
+        h->err = "unknown error";
+        return EBE_E_HIP;
+    }
+}
+
+void need_assembled(ebe_handle* h) {
+    if (!h->assembled) throw State{"ebe_assemble has not been called"};
+}
+
+void need_ptr(const void* p, const char* name) {
+    if (!p) throw Arg{std::string(name) + " is NULL"};
+}
+
+void check_launch() { HIPCHK(hipGetLastError()); }
+
+// user order -> internal order, and back
+void to_internal(ebe_handle* h, const double* user, double* internal) {
+    launch_gather3(h->stream, h->T.n_nodes, h->d_i2u, user, internal);
+}
+void to_user(ebe_handle* h, const double* internal, double* user) {
+    launch_gather3(h->stream, h->T.n_nodes, h->d_u2i, internal, user);
+}
+
+void harvest_timing(ebe_handle* h, bool wait) {
+    auto it = h->ev_pending.begin();
+    while (it != h->ev_pending.end()) {
+        if (!wait && hipEventQuery(it->second) != hipSuccess) {
+            ++it;
+            continue;
+        }
+        HIPCHK(hipEventSynchronize(it->second));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, it->first, it->second));
+        h->time_sum_ms += ms;
+        h->time_n += 1;
+        h->ev_free.push_back(it->first);
+        h->ev_free.push_back(it->second);
+        it = h->ev_pending.erase(it);
+    }
+}
+
+hipEvent_t take_event(ebe_handle* h) {
+    if (!h->ev_free.empty()) {
+        hipEvent_t e = h->ev_free.back();
+        h->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+void sync_stream(ebe_handle* h) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (!h->ev_pending.empty()) harvest_timing(h, true);
+}
+
+// Algorithm 1 on internal-order vectors: b, x (guess in, solution out).
+int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
+    hipStream_t s = h->stream;
+    const double tol = h->cfg.tol;
+    const int max_iter = h->cfg.max_iter;
+    launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
+    launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, h->partial_upd, h->counters + 1, 0, tol);
+    check_launch();
+    int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters - 2);
+    int done = DONE_RUNNING;
+    for (int guard = 0;; ++guard) {
+        for (int k = 0; k < chunk; ++k) {
+            double* pprev = h->p[h->par];
+            double* pcur = h->p[h->par ^ 1];
+            bool timed = h->timing_every > 0 && (h->pcg_launches % h->timing_every) == 0;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) {
+                e0 = take_event(h);
+                e1 = take_event(h);
+                HIPCHK(hipEventRecord(e0, s));
+            }
+            launch_ebe_pcg(s, h->dp, h->z, pprev, pcur, h->cM, h->cK, h->qbuf, h->sc, h->partial_pap, h->counters);
+            if (timed) {
+                HIPCHK(hipEventRecord(e1, s));
+                h->ev_pending.emplace_back(e0, e1);
+            }
+            h->pcg_launches++;
+            launch_pcg_update(s, h->dn, h->qbuf, pcur, h->binv6, x, h->r, h->z, h->sc, h->partial_upd,
+                              h->counters + 1, tol, max_iter);
+            h->par ^= 1;
+        }
+        // true-residual check, runs on the device only once the loop stopped
+        launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf, h->sc);
+        launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, h->partial_upd, h->counters + 1, 1,
+                        tol);
+        check_launch();
+        HIPCHK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        sync_stream(h);
+        done = h->sc_host->done;
+        if (done == DONE_RUNNING) {
+            chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters / 8);
+            if (guard > 100000) throw HipError{"PCG loop did not terminate"};
+            continue;
+        }
+        if ((done == DONE_CONVERGED || done == DONE_MAXITER) && !h->sc_host->checked) continue;
+        break;
+    }
+    const DevScalars& S = *h->sc_host;
+    if (done == DONE_ZERO_RHS) {
+        launch_zero(s, h->n3(), x);
+        check_launch();
+    }
+    if (st) {
+        st->iters = S.iters;
+        st->restarts = S.restarts;
+        st->res0 = S.res0;
+        st->bnorm = S.bnorm;
+        st->res_rec = S.bnorm > 0 ? std::sqrt(S.rr) / S.bnorm : 0.0;
+        st->res_true = S.bnorm > 0 ? S.res_true : 0.0;
+        st->status = (done == DONE_MAXITER) ? EBE_NOT_CONVERGED : EBE_OK;
+    }
+    h->last_iters = S.iters;
+    if (done == DONE_NONFINITE) {
+        h->err = "non-finite value in the PCG iteration";
+        return EBE_E_NONFINITE;
+    }
+    if (done == DONE_MAXITER) {
+        h->err = "PCG reached max_iter";
+        return EBE_NOT_CONVERGED;
+    }
+    return EBE_OK;
+}
+
+int snapshot_columns(const ebe_handle* h, int n) {
+    if (h->cfg.predictor != EBE_PRED_SNAPSHOT || h->cfg.s < 1) return 0;
+    int s_eff = std::min(h->cfg.s, n - 2);
+    return s_eff >= 1 ? s_eff : 0;
+}
+
+// Initial guess of step n = it + 1 into x; dab receives the AB4 increment.
+int predict_into(ebe_handle* h, double* x) {
+    hipStream_t s = h->stream;
+    const int n = h->it + 1;
+    launch_ab4(s, h->n3(), h->cfg.dt, h->vslot(0), h->vslot(1), h->vslot(2), h->vslot(3),
+               h->cfg.predictor == EBE_PRED_ZERO ? 0 : 1, h->dab, x);
+    int s_eff = snapshot_columns(h, n);
+    if (s_eff >= 1) {
+        ColPtrs W{};
+        const int S1 = h->cfg.s + 1;
+        for (int j = 0; j <= s_eff; ++j) {
+            int m = n - s_eff - 1 + j;  // e^m, stored in slot (m - 1) mod (s + 1)
+            W.c[j] = h->ring_slot((m - 1) % S1);
+        }
+        launch_gram_solve(s, W, s_eff, h->T.n_regions, h->d_region_start, h->cfg.drop_tol, h->coef);
+        launch_pred_apply(s, W, s_eff, h->T.n_regions, h->d_region_start, h->coef, h->dab, x);
+    }
+    check_launch();
+    return s_eff;
+}
+
+void rhs_into(ebe_handle* h, const double* f_int, const double* g, double* b) {
+    const ebe_config& c = h->cfg;
+    double g0 = g ? g[0] : 0.0, g1 = g ? g[1] : 0.0, g2 = g ? g[2] : 0.0;
+    launch_ebe_rhs(h->stream, h->dp, h->u, h->vslot(0), h->a, 4.0 / c.dt + c.rayleigh_alpha, c.rayleigh_beta, g0, g1,
+                   g2, h->qbuf);
+    launch_rhs_finalize(h->stream, h->dn, h->qbuf, f_int, b);
+    check_launch();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ebe_version(void) { return "ebe-ddpcg 0.1 (gfx950, FP64)"; }
+
+const char* ebe_last_error(const ebe_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
+    g_create_error.clear();
+    if (!cfg || !out) {
+        g_create_error = "cfg and out must not be NULL";
+        return EBE_E_INVALID_ARG;
+    }
+    *out = nullptr;
+    ebe_config c = *cfg;
+    if (!(c.dt > 0) || !(c.tol > 0) || c.s < 0 || c.s > 32 || c.predictor < 0 || c.predictor > 2 ||
+        c.rayleigh_alpha < 0 || c.rayleigh_beta < 0 || c.patch_elems > kMaxPatchElems) {
+        g_create_error = "invalid configuration (need dt > 0, tol > 0, 0 <= s <= 32, predictor in 0..2, "
+                         "non-negative damping, patch_elems <= 64)";
+        return EBE_E_INVALID_ARG;
+    }
+    if (c.max_iter <= 0) c.max_iter = 10000;
+    if (c.drop_tol <= 0) c.drop_tol = 1e-6;
+    if (c.region_nodes <= 0) c.region_nodes = 512;
+    if (c.patch_elems <= 0) c.patch_elems = kMaxPatchElems;
+    ebe_handle* h = new (std::nothrow) ebe_handle();
+    if (!h) {
+        g_create_error = "out of memory";
+        return EBE_E_NO_MEMORY;
+    }
+    h->cfg = c;
+    h->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        g_create_error = "no HIP device";
+        delete h;
+        return EBE_E_HIP;
+    }
+    h->cM = 4.0 / (c.dt * c.dt) + 2.0 * c.rayleigh_alpha / c.dt;
+    h->cK = 1.0 + 2.0 * c.rayleigh_beta / c.dt;
+    *out = h;
+    return EBE_OK;
+}
+
+int ebe_destroy(ebe_handle* h) {
+    if (!h) return EBE_OK;
+    (void)hipSetDevice(h->device);
+    h->free_all();
+    if (h->sc_host) (void)hipHostFree(h->sc_host);
+    delete h;
+    return EBE_OK;
+}
+
+int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n_elems, const int32_t* conn,
+                 const int32_t* elem_mat, int32_t n_mat, const double* mat, const uint8_t* fixed,
+                 const int32_t* region_of_node) {
+    return guarded(h, [&]() -> int {
+        need_ptr(coords, "coords");
+        need_ptr(conn, "conn");
+        need_ptr(elem_mat, "elem_mat");
+        need_ptr(mat, "mat");
+        need_ptr(fixed, "fixed");
+        h->free_all();
+        Topology& T = h->T;
+        std::string e = build_topology(T, n_nodes, coords, n_elems, conn, elem_mat, n_mat, mat, fixed,
+                                       region_of_node, h->cfg.region_nodes, h->cfg.patch_elems);
+        if (!e.empty()) throw Arg{e};
+        hipStream_t s = h->stream;
+        const int64_t N = T.n_nodes, n3 = 3 * N;
+        // topology
+        h->dp.el_ptr = h->upload(T.patch_el_ptr);
+        h->dp.pn_ptr = h->upload(T.patch_pn_ptr);
+        h->dp.nv = h->upload(T.patch_nv);
+        h->dp.nodes = h->upload(T.patch_nodes);
+        h->dp.elems = h->upload(T.elems);
+        h->dp.coords = h->upload(T.coords);
+        h->dp.mat = h->upload(T.mat_lmr);
+        uint8_t* fm = h->upload(T.fixmask);
+        h->dp.fixmask = fm;
+        h->dp.n_patches_pad = T.n_patches_pad;
+        h->dp.max_pn = T.max_pn;
+        h->dp.max_nv = T.max_nv;
+        h->dn.pn_ptr = h->upload(T.node_pn_ptr);
+        h->dn.pn = h->upload(T.node_pn);
+        h->dn.fixmask = fm;
+        h->dn.n = N;
+        h->d_i2u = h->upload(T.i2u);
+        h->d_u2i = h->upload(T.u2i);
+        h->d_region_start = h->upload(T.region_start);
+        // buffers
+        const size_t PN = T.patch_nodes.size();
+        h->qbuf = h->alloc<double>(6 * PN);  // 6 entries per slot during setup, 3 afterwards
+        h->binv6 = h->alloc<double>(6 * N);
+        h->u = h->alloc<double>(n3);
+        h->a = h->alloc<double>(n3);
+        for (int k = 0; k < 4; ++k) h->vh[k] = h->alloc<double>(n3);
+        h->ring = h->alloc<double>((size_t)(h->cfg.s + 1) * n3);
+        h->dab = h->alloc<double>(n3);
+        h->x = h->alloc<double>(n3);
+        h->b = h->alloc<double>(n3);
+        h->r = h->alloc<double>(n3);
+        h->z = h->alloc<double>(n3);
+        h->p[0] = h->alloc<double>(n3);
+        h->p[1] = h->alloc<double>(n3);
+        h->t0 = h->alloc<double>(n3);
+        h->t1 = h->alloc<double>(n3);
+        h->coef = h->alloc<double>(32 * (size_t)T.n_regions);
+        h->sc = h->alloc<DevScalars>(1);
+        h->partial_pap = h->alloc<double>(T.n_patches_pad);
+        h->partial_upd = h->alloc<double>(3 * (size_t)update_blocks(N));
+        h->counters = h->alloc<unsigned>(2);
+        if (!h->sc_host) HIPCHK(hipHostMalloc((void**)&h->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+        HIPCHK(hipMemsetAsync(h->counters, 0, 2 * sizeof(unsigned), s));
+        HIPCHK(hipMemsetAsync(h->sc, 0, sizeof(DevScalars), s));
+        // block-Jacobi inverse of A_bc
+        launch_ebe_diag(s, h->dp, h->cM, h->cK, h->qbuf);
+        launch_diag_finalize(s, h->dn, h->qbuf, h->binv6);
+        // rest state
+        launch_zero(s, n3, h->u);
+        launch_zero(s, n3, h->a);
+        for (int k = 0; k < 4; ++k) launch_zero(s, n3, h->vh[k]);
+        launch_zero(s, (int64_t)(h->cfg.s + 1) * n3, h->ring);
+        launch_zero(s, n3, h->p[0]);
+        launch_zero(s, n3, h->p[1]);
+        check_launch();
+        HIPCHK(hipStreamSynchronize(s));
+        h->head = 0;
+        h->it = 0;
+        h->par = 0;
+        h->last_iters = 0;
+        h->assembled = true;
+        return EBE_OK;
+    });
+}
+
+int ebe_get_regions(ebe_handle* h, int32_t* region_of_node, int32_t* n_regions) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (region_of_node) std::copy(h->T.region_user.begin(), h->T.region_user.end(), region_of_node);
+        if (n_regions) *n_regions = h->T.n_regions;
+        return EBE_OK;
+    });
+}
+
+int ebe_apply(ebe_handle* h, const double* p, double* q) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        need_ptr(p, "p");
+        need_ptr(q, "q");
+        to_internal(h, p, h->t0);
+        launch_ebe_apply(h->stream, h->dp, h->t0, true, h->cM, h->cK, h->qbuf);
+        launch_combine_apply(h->stream, h->dn, h->qbuf, h->t0, 1, h->t1);
+        to_user(h, h->t1, q);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_apply_mk(ebe_handle* h, double cm, double ck, const double* p, double* q) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        need_ptr(p, "p");
+        need_ptr(q, "q");
+        to_internal(h, p, h->t0);
+        launch_ebe_apply(h->stream, h->dp, h->t0, false, cm, ck, h->qbuf);
+        launch_combine_apply(h->stream, h->dn, h->qbuf, h->t0, 0, h->t1);
+        to_user(h, h->t1, q);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_precond(ebe_handle* h, const double* r, double* z) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        need_ptr(r, "r");
+        need_ptr(z, "z");
+        to_internal(h, r, h->t0);
+        launch_precond(h->stream, h->dn, h->binv6, h->t0, h->t1);
+        to_user(h, h->t1, z);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* b) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        need_ptr(b, "b");
+        const double* f_int = nullptr;
+        if (f_ext) {
+            to_internal(h, f_ext, h->t0);
+            f_int = h->t0;
+        }
+        rhs_into(h, f_int, base_acc, h->t1);
+        to_user(h, h->t1, b);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_predict(ebe_handle* h, const double* f_next, double* dxbar, int32_t* s_eff) {
+    (void)f_next;
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        need_ptr(dxbar, "dxbar");
+        int se = predict_into(h, h->t1);
+        to_user(h, h->t1, dxbar);
+        check_launch();
+        if (s_eff) *s_eff = se;
+        return EBE_OK;
+    });
+}
+
+int ebe_refine(ebe_handle* h, const double* b, double* x, ebe_solve_stats* stats) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        need_ptr(b, "b");
+        need_ptr(x, "x");
+        to_internal(h, b, h->t0);
+        to_internal(h, x, h->t1);
+        check_launch();
+        int rc = solve(h, h->t0, h->t1, stats);
+        to_user(h, h->t1, x);
+        check_launch();
+        return rc;
+    });
+}
+
+int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_step_stats* stats) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        hipStream_t s = h->stream;
+        const double* f_int = nullptr;
+        if (f_ext) {
+            to_internal(h, f_ext, h->t0);
+            f_int = h->t0;
+        }
+        rhs_into(h, f_int, base_acc, h->b);
+        const int n = h->it + 1;
+        int s_eff = predict_into(h, h->x);
+        ebe_solve_stats st{};
+        int rc = solve(h, h->b, h->x, &st);
+        if (rc < 0) return rc;
+        double* slot = h->cfg.s >= 1 ? h->ring_slot((n - 1) % (h->cfg.s + 1)) : nullptr;
+        launch_newmark(s, h->n3(), h->cfg.dt, h->x, h->dab, h->u, h->vslot(0), h->vslot(3), h->a, slot);
+        check_launch();
+        h->head = (h->head + 3) & 3;
+        h->it = n;
+        if (stats) {
+            stats->it = n;
+            stats->s_eff = s_eff;
+            stats->iters = st.iters;
+            stats->restarts = st.restarts;
+            stats->status = st.status;
+            stats->res0 = st.res0;
+            stats->res_rec = st.res_rec;
+            stats->res_true = st.res_true;
+            stats->bnorm = st.bnorm;
+        }
+        return rc;
+    });
+}
+
+int ebe_get_state(ebe_handle* h, double* u, double* v, double* a) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (u) to_user(h, h->u, u);
+        if (v) to_user(h, h->vslot(0), v);
+        if (a) to_user(h, h->a, a);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_set_state(ebe_handle* h, const double* u, const double* v, const double* a) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (u) to_internal(h, u, h->u);
+        if (v) to_internal(h, v, h->vslot(0));
+        if (a) to_internal(h, a, h->a);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        const int64_t n3 = h->n3();
+        if (vhist)
+            for (int j = 0; j < 4; ++j) to_user(h, h->vslot(j), vhist + j * n3);
+        if (ring)
+            for (int k = 0; k <= h->cfg.s; ++k) to_user(h, h->ring_slot(k), ring + k * n3);
+        if (it) *it = h->it;
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (it < 0) throw Arg{"it must be non-negative"};
+        const int64_t n3 = h->n3();
+        if (vhist)
+            for (int j = 0; j < 4; ++j) to_internal(h, vhist + j * n3, h->vslot(j));
+        if (ring)
+            for (int k = 0; k <= h->cfg.s; ++k) to_internal(h, ring + k * n3, h->ring_slot(k));
+        h->it = it;
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_sync(ebe_handle* h) {
+    return guarded(h, [&]() -> int {
+        sync_stream(h);
+        return EBE_OK;
+    });
+}
+
+int ebe_set_kernel_timing(ebe_handle* h, int32_t every_n) {
+    return guarded(h, [&]() -> int {
+        sync_stream(h);
+        h->timing_every = every_n > 0 ? every_n : 0;
+        h->time_sum_ms = 0.0;
+        h->time_n = 0;
+        h->pcg_launches = 0;
+        return EBE_OK;
+    });
+}
+
+int ebe_kernel_time(ebe_handle* h, int64_t* launches, double* mean_ms) {
+    return guarded(h, [&]() -> int {
+        sync_stream(h);
+        if (launches) *launches = h->time_n;
+        if (mean_ms) *mean_ms = h->time_n ? h->time_sum_ms / h->time_n : 0.0;
+        return EBE_OK;
+    });
+}
+
+int ebe_sizes(ebe_handle* h, int64_t* n_nodes, int64_t* n_elems, int64_t* n_patch_nodes, int64_t* n_patches) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (n_nodes) *n_nodes = h->T.n_nodes;
+        if (n_elems) *n_elems = h->T.n_elems;
+        if (n_patch_nodes) *n_patch_nodes = (int64_t)h->T.patch_nodes.size();
+        if (n_patches) *n_patches = h->T.n_patches;
+        return EBE_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// kernels.h -- launch wrappers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "topology.h"
+
+namespace ebe {
+
+// Device-side scalars of one PCG solve (Algorithm 1).
+struct DevScalars {
+    double rho;       // (z, r) of the current residual
+    double alpha;
+    double beta;      // 0 on the first trip of a CG cycle
+    double bnorm;     // ||b||
+    double rr;        // ||r||^2 of the current recursive residual
+    double res0;      // relative residual of the initial guess
+    double res_true;  // relative true residual at the last check
+    double pap;       // (p, A p) of the last trip
+    int32_t done;     // 0 running, 1 converged, 2 non-finite, 3 iteration cap, 4 zero rhs
+    int32_t iters;
+    int32_t restarts;
+    int32_t checked;  // true residual evaluated since the loop stopped
+};
+
+enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_NONFINITE = 2, DONE_MAXITER = 3, DONE_ZERO_RHS = 4 };
+
+// Device copies of the topology arrays used by the element kernels.
+struct DevPatches {
+    const int32_t* el_ptr;      // [Ppad+1]
+    const int32_t* pn_ptr;      // [Ppad+1]
+    const int32_t* nv;          // [Ppad]
+    const uint32_t* nodes;      // [PN]
+    const ElemRec* elems;       // [E]
+    const double* coords;       // [N][3]
+    const double* mat;          // [n_mat][3] lambda, mu, rho
+    const uint8_t* fixmask;     // [N]
+    int32_t n_patches_pad;
+    int32_t max_pn, max_nv;
+};
+
+struct DevNodes {
+    const int32_t* pn_ptr;      // [N+1]
+    const int32_t* pn;          // [PN]
+    const uint8_t* fixmask;     // [N]
+    int64_t n;
+};
+
+constexpr int kMaxCols = 33;    // s <= 32 input columns plus the query
+struct ColPtrs {
+    const double* c[kMaxCols];
+};
+
+// ---- element-by-element operator
+// qbuf[pn] = sum over the patch's elements of (cm M_e + ck K_e) p_e for the
+// patch's nodes; p gathered with fixed components zeroed when mask_in.
+// guard: if non-NULL, the kernel runs only when a true-residual check is due.
+void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
+                      double* qbuf, const DevScalars* guard = nullptr);
+// PCG matvec: p_cur = z + beta p_prev (beta from sc), qbuf = A_e p_cur, and the
+// grid-wide (p, A p) that yields alpha = rho / (p, A p) in sc.
+void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const double* p_prev, double* p_cur,
+                    double cm, double ck, double* qbuf, DevScalars* sc, double* partial, unsigned* counter);
+// Right-hand side operands: M part w1 = a + c1 v - g, K part w2 = c2 v - u.
+void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const double* v, const double* a,
+                    double c1, double c2, double g0, double g1, double g2, double* qbuf);
+// Block diagonal of cm M + ck K per patch node (6 symmetric entries).
+void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, double* qbuf6);
+
+// ---- node-wise kernels
+void launch_combine_apply(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, int mode, double* q);
+void launch_diag_finalize(hipStream_t s, const DevNodes& N, const double* qbuf6, double* binv6);
+void launch_precond(hipStream_t s, const DevNodes& N, const double* binv6, const double* r, double* z);
+void launch_rhs_finalize(hipStream_t s, const DevNodes& N, const double* qbuf, const double* f_ext, double* b);
+// mode 0: initial residual (also sets x = b on fixed dofs); mode 1: true-residual
+// check, runs only when due (loop stopped and not yet checked)
+void launch_residual(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, const double* binv6,
+                     double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter, int mode,
+                     double tol);
+void launch_pcg_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, const double* binv6,
+                       double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter,
+                       double tol, int max_iter);
+int update_blocks(int64_t n);
+
+// ---- predictor and time integration (all lengths in dofs, 3N)
+void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const double* v2, const double* v3,
+                const double* v4, int kind, double* dab, double* x);
+void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
+                       double drop, double* coef);
+void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
+                       const double* coef, const double* dab, double* x);
+void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, const double* dab, double* u,
+                    const double* v_old, double* v_new, double* a, double* ring_slot);
+void launch_gather3(hipStream_t s, int64_t n, const int32_t* idx, const double* in, double* out);
+void launch_zero(hipStream_t s, int64_t count, double* p);
+
+}  // namespace ebe

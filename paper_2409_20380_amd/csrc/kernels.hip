@@ -1,0 +1,909 @@
+// kernels.hip -- gfx950 kernels of the element-by-element Newmark/PCG path.
+//
+// Element-by-element matvec (Eq. EBE / Eq. eqebefem):
+//   q = sum_e P_e^T (cm M_e + ck K_e) P_e p
+// for straight 10-node tetrahedra.  One 64-wide wavefront owns one patch of
+// up to 64 elements (one element per lane): it gathers the patch's nodal
+// values into LDS once (coalesced, node-major xyz), evaluates every element
+// from its vertex coordinates, accumulates the element results with LDS
+// float64 atomics (deterministic: a single wave issues them in program
+// order), and writes one 3-vector per patch node.  Each node then sums its
+// patch slots in a fixed order (patch order), so no global atomics are used
+// and results are bitwise reproducible.
+//
+// Element operator without element matrices.  The displacement gradient of
+// a straight P2 tet is linear, so it is fixed by its values H_k at the four
+// vertices:  H_k = sum_{j != k} (4 u_kj - u_j - 3 u_k) (x) grad L_j.
+// The stress is linear too, sigma = sum_k L_k sigma_k, and with
+// int L_a L_b dV = V (1 + delta_ab) / 20 the internal forces are
+//   vertex k:     f_k  = (V/20) (4 sigma_k - S) grad L_k,
+//   edge (k, j):  f_kj = (V/5) ((sigma_k + S) grad L_j + (sigma_j + S) grad L_k),
+// with S = sum_k sigma_k.  The consistent mass uses the P2 mass table
+// (units rho V / 420: vertex diagonal 6, vertex-vertex 1, vertex-edge -4 if
+// incident else -6, edge diagonal 32, edges sharing a vertex 16, opposite 8).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace ebe {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+    // fixed butterfly order over the 64 lanes: deterministic
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// 8 XCDs receive workgroups round-robin; give each XCD a contiguous block of
+// patches so neighbouring patches (which share nodes) hit the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+    int per = nb >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+__device__ __forceinline__ void lds_add(double* p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+struct Geo {
+    double g[4][3];
+    double V;
+};
+
+// Barycentric gradients of a straight tetrahedron: rows of J^{-1} with
+// J = [x1-x0, x2-x0, x3-x0]; grad L0 = -(grad L1 + grad L2 + grad L3).
+__device__ __forceinline__ void tet_geo(const double* x0, const double* x1, const double* x2, const double* x3,
+                                        Geo& G) {
+    double a0 = x1[0] - x0[0], a1 = x2[0] - x0[0], a2 = x3[0] - x0[0];
+    double b0 = x1[1] - x0[1], b1 = x2[1] - x0[1], b2 = x3[1] - x0[1];
+    double c0 = x1[2] - x0[2], c1 = x2[2] - x0[2], c2 = x3[2] - x0[2];
+    double m00 = b1 * c2 - b2 * c1, m01 = a2 * c1 - a1 * c2, m02 = a1 * b2 - a2 * b1;
+    double m10 = b2 * c0 - b0 * c2, m11 = a0 * c2 - a2 * c0, m12 = a2 * b0 - a0 * b2;
+    double m20 = b0 * c1 - b1 * c0, m21 = a1 * c0 - a0 * c1, m22 = a0 * b1 - a1 * b0;
+    double det = a0 * m00 + a1 * m10 + a2 * m20;
+    double id = 1.0 / det;
+    G.g[1][0] = m00 * id; G.g[1][1] = m01 * id; G.g[1][2] = m02 * id;
+    G.g[2][0] = m10 * id; G.g[2][1] = m11 * id; G.g[2][2] = m12 * id;
+    G.g[3][0] = m20 * id; G.g[3][1] = m21 * id; G.g[3][2] = m22 * id;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) G.g[0][d] = -(G.g[1][d] + G.g[2][d] + G.g[3][d]);
+    G.V = det * (1.0 / 6.0);
+}
+
+// local edge index (4..9) of the vertex pair (k, j)
+__device__ __forceinline__ constexpr int edge_of(int k, int j) {
+    const int a = k < j ? k : j, b = k < j ? j : k;
+    return a == 0 ? (b == 1 ? 4 : b == 2 ? 6 : 7) : a == 1 ? (b == 2 ? 5 : 8) : 9;
+}
+
+// f[10][3] = mc * Mhat pm + K pk  (Mhat: mass table in units of rho V/420
+// scaled into mc; K with lamV = ck lam V/20, muV = ck mu V/20).
+__device__ __forceinline__ void element_apply(const double (&pm)[10][3], const double (&pk)[10][3], const Geo& G,
+                                              double lamV, double muV, double mc, double (&f)[10][3]) {
+    // ---- stiffness: vertex stresses (scaled by V/20)
+    double sg[4][6];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j == k) continue;
+            const int e = edge_of(k, j);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double d = 4.0 * pk[e][c] - pk[j][c] - 3.0 * pk[k][c];
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) H[c][dd] = fma(d, G.g[j][dd], H[c][dd]);
+            }
+        }
+        double tr = lamV * (H[0][0] + H[1][1] + H[2][2]);
+        double m2 = 2.0 * muV;
+        sg[k][0] = fma(m2, H[0][0], tr);
+        sg[k][1] = fma(m2, H[1][1], tr);
+        sg[k][2] = fma(m2, H[2][2], tr);
+        sg[k][3] = muV * (H[0][1] + H[1][0]);
+        sg[k][4] = muV * (H[0][2] + H[2][0]);
+        sg[k][5] = muV * (H[1][2] + H[2][1]);
+    }
+    double S[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) S[t] = (sg[0][t] + sg[1][t]) + (sg[2][t] + sg[3][t]);
+    // vertex forces: (4 sigma_k - S) g_k
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double t[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) t[q] = fma(4.0, sg[k][q], -S[q]);
+        const double* g = G.g[k];
+        f[k][0] = t[0] * g[0] + t[3] * g[1] + t[4] * g[2];
+        f[k][1] = t[3] * g[0] + t[1] * g[1] + t[5] * g[2];
+        f[k][2] = t[4] * g[0] + t[5] * g[1] + t[2] * g[2];
+    }
+    // edge forces: 4 ((sigma_k + S) g_j + (sigma_j + S) g_k)
+    double T[4][6];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) T[k][q] = 4.0 * (sg[k][q] + S[q]);
+    constexpr int EV[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int k = EV[m][0], j = EV[m][1];
+        const double* gj = G.g[j];
+        const double* gk = G.g[k];
+        const double* A = T[k];
+        const double* B = T[j];
+        f[4 + m][0] = A[0] * gj[0] + A[3] * gj[1] + A[4] * gj[2] + B[0] * gk[0] + B[3] * gk[1] + B[4] * gk[2];
+        f[4 + m][1] = A[3] * gj[0] + A[1] * gj[1] + A[5] * gj[2] + B[3] * gk[0] + B[1] * gk[1] + B[5] * gk[2];
+        f[4 + m][2] = A[4] * gj[0] + A[5] * gj[1] + A[2] * gj[2] + B[4] * gk[0] + B[5] * gk[1] + B[2] * gk[2];
+    }
+    // ---- consistent mass
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double p0 = pm[0][c], p1 = pm[1][c], p2 = pm[2][c], p3 = pm[3][c];
+        double p4 = pm[4][c], p5 = pm[5][c], p6 = pm[6][c], p7 = pm[7][c], p8 = pm[8][c], p9 = pm[9][c];
+        double Pv = (p0 + p1) + (p2 + p3);
+        double Pe = (p4 + p5) + (p6 + p7) + (p8 + p9);
+        double bv = Pv - 6.0 * Pe;
+        double be = 16.0 * Pe - 6.0 * Pv;
+        f[0][c] = fma(mc, fma(5.0, p0, bv) + 2.0 * (p4 + p6 + p7), f[0][c]);
+        f[1][c] = fma(mc, fma(5.0, p1, bv) + 2.0 * (p4 + p5 + p8), f[1][c]);
+        f[2][c] = fma(mc, fma(5.0, p2, bv) + 2.0 * (p5 + p6 + p9), f[2][c]);
+        f[3][c] = fma(mc, fma(5.0, p3, bv) + 2.0 * (p7 + p8 + p9), f[3][c]);
+        f[4][c] = fma(mc, be + 2.0 * (p0 + p1) + 16.0 * p4 - 8.0 * p9, f[4][c]);
+        f[5][c] = fma(mc, be + 2.0 * (p1 + p2) + 16.0 * p5 - 8.0 * p7, f[5][c]);
+        f[6][c] = fma(mc, be + 2.0 * (p0 + p2) + 16.0 * p6 - 8.0 * p8, f[6][c]);
+        f[7][c] = fma(mc, be + 2.0 * (p0 + p3) + 16.0 * p7 - 8.0 * p5, f[7][c]);
+        f[8][c] = fma(mc, be + 2.0 * (p1 + p3) + 16.0 * p8 - 8.0 * p6, f[8][c]);
+        f[9][c] = fma(mc, be + 2.0 * (p2 + p3) + 16.0 * p9 - 8.0 * p4, f[9][c]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// element-by-element kernel (one wavefront per patch)
+// ---------------------------------------------------------------------------
+enum { MODE_APPLY = 0, MODE_PCG = 1, MODE_RHS = 2 };
+
+struct EbeArgs {
+    DevPatches P;
+    const double* in0;   // APPLY: p; PCG: z; RHS: u
+    const double* in1;   // PCG: p_prev; RHS: v
+    const double* in2;   // RHS: a
+    double* p_cur;       // PCG
+    double* qbuf;
+    double cm, ck;
+    double c1, c2;       // RHS: w1 = a + c1 v - g, w2 = c2 v - u
+    double g0, g1, g2;
+    int mask_in;         // APPLY
+    DevScalars* sc;      // PCG; APPLY: optional guard (run only when a residual check is due)
+    double* partial;     // PCG
+    unsigned* counter;   // PCG
+};
+
+// True-residual check is due when the loop stopped (converged or capped) and
+// the check has not run yet.
+__device__ __forceinline__ bool check_due(const DevScalars* sc) {
+    return (sc->done == DONE_CONVERGED || sc->done == DONE_MAXITER) && !sc->checked;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64) void k_ebe(EbeArgs A) {
+    if (MODE == MODE_PCG && A.sc->done) return;
+    if (MODE == MODE_APPLY && A.sc && !check_due(A.sc)) return;
+    extern __shared__ double lds[];
+    const DevPatches& P = A.P;
+    const int lane = threadIdx.x;
+    const int patch = xcd_remap(blockIdx.x, gridDim.x);
+    const int pn0 = P.pn_ptr[patch], npn = P.pn_ptr[patch + 1] - pn0;
+    const int nv = P.nv[patch];
+    const int e0 = P.el_ptr[patch], ne = P.el_ptr[patch + 1] - e0;
+    double* lm = lds;                          // [max_pn][3] mass operand (or shared operand)
+    double* lk = lm + 3 * P.max_pn;            // [max_pn][3] stiffness operand (RHS only)
+    double* la = lk + (MODE == MODE_RHS ? 3 * P.max_pn : 0);   // [max_pn][3] accumulator
+    double* lx = la + 3 * P.max_pn;            // [max_nv][3] vertex coordinates
+
+    double beta = 0.0;
+    if (MODE == MODE_PCG) beta = A.sc->beta;
+
+    for (int j = lane; j < npn; j += 64) {
+        uint32_t ent = P.nodes[pn0 + j];
+        int g = (int)(ent & ~kOwnerBit);
+        double v0, v1, v2;
+        if (MODE == MODE_APPLY) {
+            v0 = A.in0[3 * (int64_t)g]; v1 = A.in0[3 * (int64_t)g + 1]; v2 = A.in0[3 * (int64_t)g + 2];
+            if (A.mask_in) {
+                uint8_t fm = P.fixmask[g];
+                if (fm & 1) v0 = 0.0;
+                if (fm & 2) v1 = 0.0;
+                if (fm & 4) v2 = 0.0;
+            }
+        } else if (MODE == MODE_PCG) {
+            v0 = A.in0[3 * (int64_t)g]; v1 = A.in0[3 * (int64_t)g + 1]; v2 = A.in0[3 * (int64_t)g + 2];
+            if (beta != 0.0) {
+                v0 = fma(beta, A.in1[3 * (int64_t)g], v0);
+                v1 = fma(beta, A.in1[3 * (int64_t)g + 1], v1);
+                v2 = fma(beta, A.in1[3 * (int64_t)g + 2], v2);
+            }
+            if (ent & kOwnerBit) {
+                A.p_cur[3 * (int64_t)g] = v0; A.p_cur[3 * (int64_t)g + 1] = v1; A.p_cur[3 * (int64_t)g + 2] = v2;
+            }
+        } else {  // RHS
+            double u0 = A.in0[3 * (int64_t)g], u1 = A.in0[3 * (int64_t)g + 1], u2 = A.in0[3 * (int64_t)g + 2];
+            double w0 = A.in1[3 * (int64_t)g], w1 = A.in1[3 * (int64_t)g + 1], w2 = A.in1[3 * (int64_t)g + 2];
+            double a0 = A.in2[3 * (int64_t)g], a1 = A.in2[3 * (int64_t)g + 1], a2 = A.in2[3 * (int64_t)g + 2];
+            v0 = fma(A.c1, w0, a0) - A.g0; v1 = fma(A.c1, w1, a1) - A.g1; v2 = fma(A.c1, w2, a2) - A.g2;
+            lk[3 * j] = fma(A.c2, w0, -u0); lk[3 * j + 1] = fma(A.c2, w1, -u1); lk[3 * j + 2] = fma(A.c2, w2, -u2);
+        }
+        lm[3 * j] = v0; lm[3 * j + 1] = v1; lm[3 * j + 2] = v2;
+        la[3 * j] = 0.0; la[3 * j + 1] = 0.0; la[3 * j + 2] = 0.0;
+        if (j < nv) {
+            lx[3 * j] = P.coords[3 * (int64_t)g];
+            lx[3 * j + 1] = P.coords[3 * (int64_t)g + 1];
+            lx[3 * j + 2] = P.coords[3 * (int64_t)g + 2];
+        }
+    }
+    __syncthreads();
+
+    double pap = 0.0;
+    if (lane < ne) {
+        const ElemRec rec = P.elems[e0 + lane];
+        Geo G;
+        tet_geo(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
+        const double* mp = P.mat + 3 * rec.mat;
+        double w = G.V * (1.0 / 20.0) * A.ck;
+        double lamV = mp[0] * w, muV = mp[1] * w;
+        double mc = A.cm * mp[2] * G.V * (1.0 / 420.0);
+        double pm[10][3], pk[10][3], f[10][3];
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            const int l = rec.lid[i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pm[i][c] = lm[3 * l + c];
+        }
+        if (MODE == MODE_RHS) {
+#pragma unroll
+            for (int i = 0; i < 10; ++i) {
+                const int l = rec.lid[i];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pk[i][c] = lk[3 * l + c];
+            }
+            element_apply(pm, pk, G, lamV, muV, mc, f);
+        } else {
+            element_apply(pm, pm, G, lamV, muV, mc, f);
+        }
+#pragma unroll
+        for (int i = 0; i < 10; ++i) {
+            const int l = rec.lid[i];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                lds_add(la + 3 * l + c, f[i][c]);
+                if (MODE == MODE_PCG) pap = fma(pm[i][c], f[i][c], pap);
+            }
+        }
+    }
+    __syncthreads();
+    for (int j = lane; j < npn; j += 64) {
+        double* q = A.qbuf + 3 * (int64_t)(pn0 + j);
+        q[0] = la[3 * j]; q[1] = la[3 * j + 1]; q[2] = la[3 * j + 2];
+    }
+
+    if (MODE == MODE_PCG) {
+        pap = wave_sum(pap);
+        __shared__ int is_last;
+        if (lane == 0) {
+            A.partial[patch] = pap;
+            __threadfence();
+            unsigned t = __hip_atomic_fetch_add(A.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            is_last = (t == gridDim.x - 1);
+        }
+        __syncthreads();
+        if (is_last) {
+            __threadfence();
+            double s = 0.0;
+            for (int i = lane; i < (int)gridDim.x; i += 64)
+                s += __hip_atomic_load(A.partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s = wave_sum(s);
+            if (lane == 0) {
+                DevScalars* sc = A.sc;
+                sc->pap = s;
+                double alpha = sc->rho / s;
+                sc->alpha = alpha;
+                if (!isfinite(alpha)) sc->done = DONE_NONFINITE;
+                *A.counter = 0u;
+                __threadfence();
+            }
+        }
+    }
+}
+
+static size_t ebe_lds_bytes(const DevPatches& P, int mode) {
+    return sizeof(double) * (size_t)(3 * P.max_pn * (mode == MODE_RHS ? 3 : 2) + 3 * P.max_nv);
+}
+
+void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
+                      double* qbuf, const DevScalars* guard) {
+    EbeArgs A{};
+    A.P = P; A.in0 = p; A.qbuf = qbuf; A.cm = cm; A.ck = ck; A.mask_in = mask_in ? 1 : 0;
+    A.sc = const_cast<DevScalars*>(guard);
+    hipLaunchKernelGGL(k_ebe<MODE_APPLY>, dim3(P.n_patches_pad), dim3(64), ebe_lds_bytes(P, MODE_APPLY), s, A);
+}
+
+void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const double* p_prev, double* p_cur,
+                    double cm, double ck, double* qbuf, DevScalars* sc, double* partial, unsigned* counter) {
+    EbeArgs A{};
+    A.P = P; A.in0 = z; A.in1 = p_prev; A.p_cur = p_cur; A.qbuf = qbuf; A.cm = cm; A.ck = ck;
+    A.sc = sc; A.partial = partial; A.counter = counter;
+    hipLaunchKernelGGL(k_ebe<MODE_PCG>, dim3(P.n_patches_pad), dim3(64), ebe_lds_bytes(P, MODE_PCG), s, A);
+}
+
+void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const double* v, const double* a,
+                    double c1, double c2, double g0, double g1, double g2, double* qbuf) {
+    EbeArgs A{};
+    A.P = P; A.in0 = u; A.in1 = v; A.in2 = a; A.qbuf = qbuf; A.cm = 1.0; A.ck = 1.0;
+    A.c1 = c1; A.c2 = c2; A.g0 = g0; A.g1 = g1; A.g2 = g2;
+    hipLaunchKernelGGL(k_ebe<MODE_RHS>, dim3(P.n_patches_pad), dim3(64), ebe_lds_bytes(P, MODE_RHS), s, A);
+}
+
+// ---------------------------------------------------------------------------
+// block diagonal of cm M + ck K (setup)
+// ---------------------------------------------------------------------------
+// Node-diagonal 3x3 blocks: int gradN_i (x) gradN_i is
+//   vertex i:    (3/5) V g_i g_i^T            (gradN_i = (4 L_i - 1) g_i)
+//   edge (i,j):  (8/5) V (g_i g_i^T + g_j g_j^T) + (4/5) V (g_i g_j^T + g_j g_i^T)
+// K_ii = (lam + mu) G + mu tr(G) I; M_ii = rho V {6, 32}/420.
+__global__ __launch_bounds__(64) void k_ebe_diag(DevPatches P, double cm, double ck, double* qbuf6) {
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int patch = xcd_remap(blockIdx.x, gridDim.x);
+    const int pn0 = P.pn_ptr[patch], npn = P.pn_ptr[patch + 1] - pn0;
+    const int nv = P.nv[patch];
+    const int e0 = P.el_ptr[patch], ne = P.el_ptr[patch + 1] - e0;
+    double* la = lds;                 // [max_pn][6]
+    double* lx = la + 6 * P.max_pn;   // [max_nv][3]
+    for (int j = lane; j < npn; j += 64) {
+        int g = (int)(P.nodes[pn0 + j] & ~kOwnerBit);
+        for (int t = 0; t < 6; ++t) la[6 * j + t] = 0.0;
+        if (j < nv)
+            for (int d = 0; d < 3; ++d) lx[3 * j + d] = P.coords[3 * (int64_t)g + d];
+    }
+    __syncthreads();
+    if (lane < ne) {
+        const ElemRec rec = P.elems[e0 + lane];
+        Geo Gm;
+        tet_geo(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], Gm);
+        const double* mp = P.mat + 3 * rec.mat;
+        double lam = ck * mp[0], mu = ck * mp[1], rho = cm * mp[2];
+        double V = Gm.V;
+        constexpr int EV[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+        for (int i = 0; i < 10; ++i) {
+            double G[3][3];
+            double mdiag;
+            if (i < 4) {
+                const double* g = Gm.g[i];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) G[a][b] = 0.6 * V * g[a] * g[b];
+                mdiag = rho * V * (6.0 / 420.0);
+            } else {
+                const double* gi = Gm.g[EV[i - 4][0]];
+                const double* gj = Gm.g[EV[i - 4][1]];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        G[a][b] = 1.6 * V * (gi[a] * gi[b] + gj[a] * gj[b]) + 0.8 * V * (gi[a] * gj[b] + gj[a] * gi[b]);
+                mdiag = rho * V * (32.0 / 420.0);
+            }
+            double tr = G[0][0] + G[1][1] + G[2][2];
+            double lm = lam + mu;
+            double* acc = la + 6 * rec.lid[i];
+            lds_add(acc + 0, lm * G[0][0] + mu * tr + mdiag);
+            lds_add(acc + 1, lm * G[1][1] + mu * tr + mdiag);
+            lds_add(acc + 2, lm * G[2][2] + mu * tr + mdiag);
+            lds_add(acc + 3, lm * G[0][1]);
+            lds_add(acc + 4, lm * G[0][2]);
+            lds_add(acc + 5, lm * G[1][2]);
+        }
+    }
+    __syncthreads();
+    for (int j = lane; j < npn; j += 64)
+        for (int t = 0; t < 6; ++t) qbuf6[6 * (int64_t)(pn0 + j) + t] = la[6 * j + t];
+}
+
+void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, double* qbuf6) {
+    size_t lds = sizeof(double) * (size_t)(6 * P.max_pn + 3 * P.max_nv);
+    hipLaunchKernelGGL(k_ebe_diag, dim3(P.n_patches_pad), dim3(64), lds, s, P, cm, ck, qbuf6);
+}
+
+// ---------------------------------------------------------------------------
+// node-wise kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void gather_q(const DevNodes& N, const double* qbuf, int64_t n, double& q0, double& q1,
+                                         double& q2) {
+    q0 = q1 = q2 = 0.0;
+    const int k0 = N.pn_ptr[n], k1 = N.pn_ptr[n + 1];
+    for (int k = k0; k < k1; ++k) {
+        const double* q = qbuf + 3 * (int64_t)N.pn[k];
+        q0 += q[0]; q1 += q[1]; q2 += q[2];
+    }
+}
+
+// mode 0: q = sum (no constraint handling); mode 1: A_bc (free rows: sum, fixed: identity p)
+__global__ void k_combine_apply(DevNodes N, const double* qbuf, const double* p, int mode, double* q) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N.n) return;
+    double q0, q1, q2;
+    gather_q(N, qbuf, n, q0, q1, q2);
+    if (mode == 1) {
+        uint8_t fm = N.fixmask[n];
+        if (fm & 1) q0 = p[3 * n];
+        if (fm & 2) q1 = p[3 * n + 1];
+        if (fm & 4) q2 = p[3 * n + 2];
+    }
+    q[3 * n] = q0; q[3 * n + 1] = q1; q[3 * n + 2] = q2;
+}
+
+void launch_combine_apply(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, int mode, double* q) {
+    int nb = (int)((N.n + 255) / 256);
+    hipLaunchKernelGGL(k_combine_apply, dim3(nb), dim3(256), 0, s, N, qbuf, p, mode, q);
+}
+
+// symmetric 3x3 inverse of the constrained block Z B Z + (I - Z), then fixed
+// rows/columns zeroed: z = binv r is zero on fixed dofs.
+__global__ void k_diag_finalize(DevNodes N, const double* qbuf6, double* binv6) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N.n) return;
+    double b[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = N.pn_ptr[n]; k < N.pn_ptr[n + 1]; ++k)
+        for (int t = 0; t < 6; ++t) b[t] += qbuf6[6 * (int64_t)N.pn[k] + t];
+    uint8_t fm = N.fixmask[n];
+    bool f0 = fm & 1, f1 = fm & 2, f2 = fm & 4;
+    double xx = f0 ? 1.0 : b[0], yy = f1 ? 1.0 : b[1], zz = f2 ? 1.0 : b[2];
+    double xy = (f0 || f1) ? 0.0 : b[3], xz = (f0 || f2) ? 0.0 : b[4], yz = (f1 || f2) ? 0.0 : b[5];
+    double c00 = yy * zz - yz * yz, c01 = xz * yz - xy * zz, c02 = xy * yz - xz * yy;
+    double c11 = xx * zz - xz * xz, c12 = xy * xz - xx * yz, c22 = xx * yy - xy * xy;
+    double det = xx * c00 + xy * c01 + xz * c02;
+    double id = 1.0 / det;
+    double r[6] = {c00 * id, c11 * id, c22 * id, c01 * id, c02 * id, c12 * id};
+    if (f0) { r[0] = 0; r[3] = 0; r[4] = 0; }
+    if (f1) { r[1] = 0; r[3] = 0; r[5] = 0; }
+    if (f2) { r[2] = 0; r[4] = 0; r[5] = 0; }
+    for (int t = 0; t < 6; ++t) binv6[6 * n + t] = r[t];
+}
+
+void launch_diag_finalize(hipStream_t s, const DevNodes& N, const double* qbuf6, double* binv6) {
+    int nb = (int)((N.n + 255) / 256);
+    hipLaunchKernelGGL(k_diag_finalize, dim3(nb), dim3(256), 0, s, N, qbuf6, binv6);
+}
+
+__device__ __forceinline__ void apply_binv(const double* B, double r0, double r1, double r2, double& z0, double& z1,
+                                           double& z2) {
+    z0 = B[0] * r0 + B[3] * r1 + B[4] * r2;
+    z1 = B[3] * r0 + B[1] * r1 + B[5] * r2;
+    z2 = B[4] * r0 + B[5] * r1 + B[2] * r2;
+}
+
+// z = B^{-1} r for the constrained operator: identity on fixed dofs
+__global__ void k_precond(DevNodes N, const double* binv6, const double* r, double* z) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N.n) return;
+    double z0, z1, z2;
+    apply_binv(binv6 + 6 * n, r[3 * n], r[3 * n + 1], r[3 * n + 2], z0, z1, z2);
+    uint8_t fm = N.fixmask[n];
+    if (fm & 1) z0 = r[3 * n];
+    if (fm & 2) z1 = r[3 * n + 1];
+    if (fm & 4) z2 = r[3 * n + 2];
+    z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
+}
+
+void launch_precond(hipStream_t s, const DevNodes& N, const double* binv6, const double* r, double* z) {
+    int nb = (int)((N.n + 255) / 256);
+    hipLaunchKernelGGL(k_precond, dim3(nb), dim3(256), 0, s, N, binv6, r, z);
+}
+
+// b = (sum of patch slots) + f_ext on free dofs, 0 on fixed dofs
+__global__ void k_rhs_finalize(DevNodes N, const double* qbuf, const double* f_ext, double* b) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N.n) return;
+    double q0, q1, q2;
+    gather_q(N, qbuf, n, q0, q1, q2);
+    if (f_ext) { q0 += f_ext[3 * n]; q1 += f_ext[3 * n + 1]; q2 += f_ext[3 * n + 2]; }
+    uint8_t fm = N.fixmask[n];
+    b[3 * n] = (fm & 1) ? 0.0 : q0;
+    b[3 * n + 1] = (fm & 2) ? 0.0 : q1;
+    b[3 * n + 2] = (fm & 4) ? 0.0 : q2;
+}
+
+void launch_rhs_finalize(hipStream_t s, const DevNodes& N, const double* qbuf, const double* f_ext, double* b) {
+    int nb = (int)((N.n + 255) / 256);
+    hipLaunchKernelGGL(k_rhs_finalize, dim3(nb), dim3(256), 0, s, N, qbuf, f_ext, b);
+}
+
+// Deterministic block reduction of NV values over 256 threads; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+    __shared__ double red[4][NV];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) v[t] = wave_sum(v[t]);
+    if (lane == 0)
+#pragma unroll
+        for (int t = 0; t < NV; ++t) red[w][t] = v[t];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int t = 0; t < NV; ++t) v[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+}
+
+// Last-block epilogue: sum NV partial arrays (stride gridDim.x) in fixed order.
+template <int NV>
+__device__ __forceinline__ bool last_block_sum(const double (&v)[NV], double* partial, unsigned* counter,
+                                               double (&tot)[NV]) {
+    __shared__ int is_last;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) partial[t * gridDim.x + blockIdx.x] = v[t];
+        __threadfence();
+        unsigned k = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (k == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double s[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) s[t] = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+#pragma unroll
+        for (int t = 0; t < NV; ++t)
+            s[t] += __hip_atomic_load(partial + t * gridDim.x + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    block_sum<NV>(s);
+#pragma unroll
+    for (int t = 0; t < NV; ++t) tot[t] = s[t];
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+// r = b - A x (from the slots), z = B^{-1} r, and (z,r), (r,r), (b,b).
+// mode 0 (initial): sets bnorm, res0, rho, beta = 0, iters = 0, done.
+// mode 1 (true-residual check): sets res_true; restarts the cycle when it
+// is not below tol (rho = (z,r), beta = 0, done = 0).
+__global__ __launch_bounds__(256) void k_residual(DevNodes N, const double* qbuf, const double* b, const double* binv6,
+                                                  double* x, double* r, double* z, DevScalars* sc, double* partial,
+                                                  unsigned* counter, int mode, double tol) {
+    if (mode == 1 && !check_due(sc)) return;
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (n < N.n) {
+        double q0, q1, q2;
+        gather_q(N, qbuf, n, q0, q1, q2);
+        uint8_t fm = N.fixmask[n];
+        double b0 = b[3 * n], b1 = b[3 * n + 1], b2 = b[3 * n + 2];
+        if (mode == 0 && fm) {  // fixed rows of A_bc are identity: x = b there, exactly
+            if (fm & 1) x[3 * n] = b0;
+            if (fm & 2) x[3 * n + 1] = b1;
+            if (fm & 4) x[3 * n + 2] = b2;
+        }
+        double r0 = (fm & 1) ? 0.0 : b0 - q0;
+        double r1 = (fm & 2) ? 0.0 : b1 - q1;
+        double r2 = (fm & 4) ? 0.0 : b2 - q2;
+        double z0, z1, z2;
+        apply_binv(binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
+        r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
+        z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
+        v[0] = z0 * r0 + z1 * r1 + z2 * r2;
+        v[1] = r0 * r0 + r1 * r1 + r2 * r2;
+        v[2] = b0 * b0 + b1 * b1 + b2 * b2;
+    }
+    block_sum<3>(v);
+    double tot[3];
+    if (last_block_sum<3>(v, partial, counter, tot) && threadIdx.x == 0) {
+        if (mode == 0) {
+            double bn = sqrt(tot[2]);
+            sc->bnorm = bn;
+            sc->rr = tot[1];
+            sc->rho = tot[0];
+            sc->beta = 0.0;
+            sc->iters = 0;
+            sc->restarts = 0;
+            sc->res_true = 0.0;
+            sc->checked = 0;
+            double res = bn > 0 ? sqrt(tot[1]) / bn : 0.0;
+            sc->res0 = res;
+            if (bn == 0.0) sc->done = DONE_ZERO_RHS;
+            else if (!isfinite(res) || !isfinite(tot[0])) sc->done = DONE_NONFINITE;
+            else sc->done = (res < tol) ? DONE_CONVERGED : DONE_RUNNING;
+        } else {
+            double res = sqrt(tot[1]) / sc->bnorm;
+            sc->res_true = res;
+            sc->checked = 1;
+            if (!isfinite(res)) sc->done = DONE_NONFINITE;
+            else if (res >= tol && sc->done == DONE_CONVERGED) {
+                sc->checked = 0;
+                sc->rr = tot[1];
+                sc->rho = tot[0];
+                sc->beta = 0.0;
+                sc->restarts += 1;
+                sc->done = DONE_RUNNING;
+            }
+        }
+        __threadfence();
+    }
+}
+
+void launch_residual(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, const double* binv6,
+                     double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter, int mode,
+                     double tol) {
+    hipLaunchKernelGGL(k_residual, dim3(update_blocks(N.n)), dim3(256), 0, s, N, qbuf, b, binv6, x, r, z, sc, partial,
+                       counter, mode, tol);
+}
+
+int update_blocks(int64_t n) { return (int)((n + 255) / 256); }
+
+// One trip of Algorithm 1 after the matvec: r -= alpha q, x += alpha p,
+// z = B^{-1} r, then (z, r) and (r, r).  The last block applies the stop test
+// ||r|| / ||b|| < tol and forms beta = (z,r)_new / (z,r)_old.
+__global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qbuf, const double* p,
+                                                    const double* binv6, double* x, double* r, double* z,
+                                                    DevScalars* sc, double* partial, unsigned* counter, double tol,
+                                                    int max_iter) {
+    if (sc->done) return;
+    const double alpha = sc->alpha;
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (n < N.n) {
+        double q0, q1, q2;
+        gather_q(N, qbuf, n, q0, q1, q2);
+        uint8_t fm = N.fixmask[n];
+        if (fm & 1) q0 = 0.0;
+        if (fm & 2) q1 = 0.0;
+        if (fm & 4) q2 = 0.0;
+        double r0 = fma(-alpha, q0, r[3 * n]);
+        double r1 = fma(-alpha, q1, r[3 * n + 1]);
+        double r2 = fma(-alpha, q2, r[3 * n + 2]);
+        x[3 * n] = fma(alpha, p[3 * n], x[3 * n]);
+        x[3 * n + 1] = fma(alpha, p[3 * n + 1], x[3 * n + 1]);
+        x[3 * n + 2] = fma(alpha, p[3 * n + 2], x[3 * n + 2]);
+        double z0, z1, z2;
+        apply_binv(binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
+        r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
+        z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
+        v[0] = z0 * r0 + z1 * r1 + z2 * r2;
+        v[1] = r0 * r0 + r1 * r1 + r2 * r2;
+    }
+    block_sum<2>(v);
+    double tot[2];
+    if (last_block_sum<2>(v, partial, counter, tot) && threadIdx.x == 0) {
+        sc->iters += 1;
+        sc->rr = tot[1];
+        double res = sqrt(tot[1]) / sc->bnorm;
+        if (!isfinite(res) || !isfinite(tot[0])) {
+            sc->done = DONE_NONFINITE;
+        } else if (res < tol) {
+            sc->done = DONE_CONVERGED;
+        } else if (sc->iters >= max_iter) {
+            sc->done = DONE_MAXITER;
+        } else {
+            sc->beta = tot[0] / sc->rho;
+            sc->rho = tot[0];
+        }
+        __threadfence();
+    }
+}
+
+void launch_pcg_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, const double* binv6,
+                       double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter,
+                       double tol, int max_iter) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(update_blocks(N.n)), dim3(256), 0, s, N, qbuf, p, binv6, x, r, z, sc,
+                       partial, counter, tol, max_iter);
+}
+
+// ---------------------------------------------------------------------------
+// predictor
+// ---------------------------------------------------------------------------
+// Adams-Bashforth 4-step increment: dab = dt/24 (55 v1 - 59 v2 + 37 v3 - 9 v4);
+// x = dab (kind >= 1) or 0 (kind 0).
+__global__ void k_ab4(int64_t n3, double dt, const double* v1, const double* v2, const double* v3, const double* v4,
+                      int kind, double* dab, double* x) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    double w = dt * (1.0 / 24.0);
+    double d = w * (55.0 * v1[i] - 59.0 * v2[i] + 37.0 * v3[i] - 9.0 * v4[i]);
+    dab[i] = d;
+    if (x) x[i] = kind == 0 ? 0.0 : d;
+}
+
+void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const double* v2, const double* v3,
+                const double* v4, int kind, double* dab, double* x) {
+    int nb = (int)((n3 + 255) / 256);
+    hipLaunchKernelGGL(k_ab4, dim3(nb), dim3(256), 0, s, n3, dt, v1, v2, v3, v4, kind, dab, x);
+}
+
+// Regional Gram products on FP64 MFMA (v_mfma_f64_16x16x4f64) followed by the
+// least-squares solve.  W = [x_1 .. x_s, q]: X^T X comes from 16x16 tiles,
+// X^T q from per-lane FMAs.  The s x s system is solved by a Cholesky
+// factorisation taken column by column in time order; a column whose
+// remaining (orthogonal) part falls below drop * its norm is dropped, which
+// reproduces the column selection of modified Gram-Schmidt in that order.
+template <int NB>
+__global__ __launch_bounds__(256) void k_gram_solve(ColPtrs W, int s_eff, const int32_t* region_start, double drop,
+                                                    double* coef) {
+    constexpr int NC = 16 * NB;
+    __shared__ double G[NC][NC + 1];
+    __shared__ double Gw[4][NB * (NB + 1) / 2][4][64];
+    __shared__ double hq[4][NC];
+    __shared__ double h[NC];
+    const int r = blockIdx.x;
+    const int64_t d0 = 3 * (int64_t)region_start[r], d1 = 3 * (int64_t)region_start[r + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, krow = lane >> 4;
+    const double* A0 = col < s_eff ? W.c[col] : nullptr;
+    const double* A1 = (NB == 2 && 16 + col < s_eff) ? W.c[16 + col] : nullptr;
+    const double* Q = W.c[s_eff];
+    double4_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
+    double h0 = 0.0, h1 = 0.0;
+    for (int64_t base = d0 + 4 * wave; base < d1; base += 16) {
+        int64_t row = base + krow;
+        bool ok = row < d1;
+        double a0 = (ok && A0) ? A0[row] : 0.0;
+        double a1 = (NB == 2 && ok && A1) ? A1[row] : 0.0;
+        double q = ok ? Q[row] : 0.0;
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, c00, 0, 0, 0);
+        if (NB == 2) {
+            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, c01, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, c11, 0, 0, 0);
+        }
+        h0 = fma(a0, q, h0);
+        h1 = fma(a1, q, h1);
+    }
+    // per-wave tiles to LDS: register v of lane l holds D[l/16 + 4 v][l%16]
+    for (int v = 0; v < 4; ++v) {
+        Gw[wave][0][v][lane] = c00[v];
+        if (NB == 2) {
+            Gw[wave][1][v][lane] = c01[v];
+            Gw[wave][2][v][lane] = c11[v];
+        }
+    }
+    h0 += __shfl_xor(h0, 16, 64);
+    h0 += __shfl_xor(h0, 32, 64);
+    h1 += __shfl_xor(h1, 16, 64);
+    h1 += __shfl_xor(h1, 32, 64);
+    if (lane < 16) {
+        hq[wave][lane] = h0;
+        if (NB == 2) hq[wave][16 + lane] = h1;
+    }
+    __syncthreads();
+    // sum over waves (fixed order) and assemble the symmetric Gram
+    for (int idx = threadIdx.x; idx < 4 * 64 * (NB * (NB + 1) / 2); idx += 256) {
+        int t = idx / 256, rem = idx % 256, v = rem / 64, l = rem % 64;
+        double s = (Gw[0][t][v][l] + Gw[1][t][v][l]) + (Gw[2][t][v][l] + Gw[3][t][v][l]);
+        int i = (l / 16) + 4 * v, j = l % 16;
+        int bi = (t == 2) ? 1 : 0, bj = (t == 0) ? 0 : 1;
+        G[16 * bi + i][16 * bj + j] = s;
+        if (bi != bj) G[16 * bj + j][16 * bi + i] = s;
+    }
+    if (threadIdx.x < NC) h[threadIdx.x] = (hq[0][threadIdx.x] + hq[1][threadIdx.x]) + (hq[2][threadIdx.x] + hq[3][threadIdx.x]);
+    __syncthreads();
+    // Column scaling, Cholesky with the time-ordered drop rule and the two
+    // triangular solves run on wave 0; the other waves only join the barriers.
+    const bool w0 = (wave == 0);
+    const int s = s_eff;
+    __shared__ double dsc[NC];
+    __shared__ int keep[NC];
+    double d = (w0 && lane < s) ? sqrt(G[lane][lane]) : 0.0;
+    if (w0 && lane < NC) dsc[lane] = d;
+    __syncthreads();
+    if (w0 && lane < s)
+        for (int i = 0; i < s; ++i) {
+            double di = dsc[i];
+            G[i][lane] = (di > 0 && d > 0) ? G[i][lane] / (di * d) : 0.0;
+        }
+    if (w0 && lane < NC) keep[lane] = 0;
+    __syncthreads();
+    const double drop2 = drop * drop;
+    for (int j = 0; j < s; ++j) {
+        double t = G[j][j];
+        bool kj = (dsc[j] > 0) && (t >= drop2);
+        double rjj = kj ? sqrt(t) : 0.0;
+        __syncthreads();
+        // row j of R: R[j][k] = G[j][k] / rjj for k > j
+        if (w0 && lane > j && lane < s) G[j][lane] = kj ? G[j][lane] / rjj : 0.0;
+        if (w0 && lane == 0) {
+            G[j][j] = rjj;
+            keep[j] = kj;
+        }
+        __syncthreads();
+        // trailing update: G[k][l] -= R[j][k] R[j][l], k, l > j (lanes over l)
+        if (w0 && kj && lane > j && lane < s)
+            for (int k = j + 1; k < s; ++k) G[k][lane] -= G[j][k] * G[j][lane];
+        __syncthreads();
+    }
+    // forward solve R^T y = h_scaled (sequential, lane 0), back solve R a = y
+    if (w0 && lane == 0) {
+        double y[NC];
+        for (int j = 0; j < s; ++j) {
+            double t = h[j] / (dsc[j] > 0 ? dsc[j] : 1.0);
+            for (int i = 0; i < j; ++i) t -= G[i][j] * y[i];
+            y[j] = keep[j] ? t / G[j][j] : 0.0;
+        }
+        for (int j = s - 1; j >= 0; --j) {
+            double t = y[j];
+            for (int k = j + 1; k < s; ++k) t -= G[j][k] * y[k];
+            y[j] = keep[j] ? t / G[j][j] : 0.0;
+        }
+        for (int j = 0; j < 32; ++j) coef[32 * (int64_t)r + j] = (j < s && keep[j]) ? y[j] / dsc[j] : 0.0;
+    }
+}
+
+void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
+                       double drop, double* coef) {
+    if (s_eff <= 16)
+        hipLaunchKernelGGL(k_gram_solve<1>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, drop, coef);
+    else
+        hipLaunchKernelGGL(k_gram_solve<2>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, drop, coef);
+}
+
+// x = dab + sum_j a_j y_j on each region, y_j = W.c[j + 1] (outputs).
+__global__ __launch_bounds__(256) void k_pred_apply(ColPtrs W, int s_eff, const int32_t* region_start,
+                                                    const double* coef, const double* dab, double* x) {
+    const int r = blockIdx.x;
+    const int64_t d0 = 3 * (int64_t)region_start[r], d1 = 3 * (int64_t)region_start[r + 1];
+    const double* a = coef + 32 * (int64_t)r;
+    for (int64_t i = d0 + threadIdx.x; i < d1; i += 256) {
+        double t = dab[i];
+        for (int j = 0; j < s_eff; ++j) t = fma(a[j], W.c[j + 1][i], t);
+        x[i] = t;
+    }
+}
+
+void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
+                       const double* coef, const double* dab, double* x) {
+    hipLaunchKernelGGL(k_pred_apply, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, coef, dab, x);
+}
+
+// Newmark-beta (beta = 1/4, gamma = 1/2): u += du; v' = -v + (2/dt) du;
+// a' = -a - (4/dt) v + (4/dt^2) du; AB error du - dab into the ring slot.
+__global__ void k_newmark(int64_t n3, double dt, const double* du, const double* dab, double* u, const double* v_old,
+                          double* v_new, double* a, double* ring_slot) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    double d = du[i], vo = v_old[i];
+    u[i] += d;
+    v_new[i] = fma(2.0 / dt, d, -vo);
+    a[i] = fma(4.0 / (dt * dt), d, fma(-4.0 / dt, vo, -a[i]));
+    if (ring_slot) ring_slot[i] = d - dab[i];
+}
+
+void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, const double* dab, double* u,
+                    const double* v_old, double* v_new, double* a, double* ring_slot) {
+    int nb = (int)((n3 + 255) / 256);
+    hipLaunchKernelGGL(k_newmark, dim3(nb), dim3(256), 0, s, n3, dt, du, dab, u, v_old, v_new, a, ring_slot);
+}
+
+__global__ void k_gather3(int64_t n, const int32_t* idx, const double* in, double* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t j = idx[i];
+    out[3 * i] = in[3 * j]; out[3 * i + 1] = in[3 * j + 1]; out[3 * i + 2] = in[3 * j + 2];
+}
+
+void launch_gather3(hipStream_t s, int64_t n, const int32_t* idx, const double* in, double* out) {
+    int nb = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_gather3, dim3(nb), dim3(256), 0, s, n, idx, in, out);
+}
+
+__global__ void k_zero(int64_t n, double* p) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+void launch_zero(hipStream_t s, int64_t count, double* p) {
+    int nb = (int)((count + 255) / 256);
+    hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, s, count, p);
+}
+
+}  // namespace ebe

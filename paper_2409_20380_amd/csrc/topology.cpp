@@ -1,0 +1,253 @@
+// topology.cpp -- host-side preprocessing of the mesh for the EBE kernels.
+//
+// Internal node order: nodes sorted by (predictor region, Morton code of the
+// position), so every region is one contiguous range of the state vectors and
+// nodes that are close in space are close in memory.
+// Element order: by the lowest internal id among the element's vertices,
+// ties broken by the Morton code of the centroid.  Consecutive runs of
+// patch_elems elements form a patch; a patch is processed by one 64-wide
+// wavefront that stages the patch's nodes in LDS.  Each patch lists its nodes
+// (vertices first, so the geometry gather touches a prefix only) and every
+// node lists the patch slots it receives contributions from, in patch order,
+// which fixes the summation order and makes results bitwise reproducible.
+#include "topology.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+
+namespace ebe {
+
+static const int kEdge[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
+
+static uint64_t spread3(uint64_t x) {
+    x &= 0x1fffff;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+namespace {
+struct Box {
+    double lo[3], hi[3];
+    uint64_t morton(const double* p) const {
+        uint64_t c = 0;
+        for (int d = 0; d < 3; ++d) {
+            double ext = hi[d] - lo[d];
+            double t = ext > 0 ? (p[d] - lo[d]) / ext : 0.0;
+            uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(t * 2097151.0)));
+            c |= spread3(q) << d;
+        }
+        return c;
+    }
+};
+}  // namespace
+
+static char g_buf[512];
+template <class... A>
+static std::string fmt(const char* f, A... a) {
+    std::snprintf(g_buf, sizeof(g_buf), f, a...);
+    return std::string(g_buf);
+}
+
+std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, const int32_t* conn,
+                           const int32_t* elem_mat, int32_t n_mat, const double* mat, const uint8_t* fixed,
+                           const int32_t* region_of_node, int region_nodes, int patch_elems) {
+    if (N <= 0 || E <= 0) return "mesh must have nodes and elements";
+    if (N >= (int64_t)1 << 31 || E >= (int64_t)1 << 31) return "mesh too large for 32-bit ids";
+    if (n_mat <= 0 || n_mat > 65535) return "n_mat must be in [1, 65535]";
+    if (patch_elems <= 0 || patch_elems > kMaxPatchElems) return "patch_elems must be in [1, 64]";
+    T = Topology();
+    T.n_nodes = N;
+    T.n_elems = E;
+
+    // ---- materials
+    T.mat_lmr.resize(3 * (size_t)n_mat);
+    for (int m = 0; m < n_mat; ++m) {
+        double rho = mat[3 * m], vp = mat[3 * m + 1], vs = mat[3 * m + 2];
+        double mu = rho * vs * vs, lam = rho * (vp * vp - 2.0 * vs * vs);
+        if (!(rho > 0) || !(vs > 0) || !(lam + 2.0 * mu / 3.0 > 0) || !std::isfinite(lam))
+            return fmt("material %d is not a valid isotropic elastic solid", m);
+        T.mat_lmr[3 * m] = lam;
+        T.mat_lmr[3 * m + 1] = mu;
+        T.mat_lmr[3 * m + 2] = rho;
+    }
+
+    // ---- element validation: ids, orientation, midpoint edge nodes; vertex/edge roles
+    std::vector<uint8_t> role(N, 0);  // bit0 vertex, bit1 edge
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t* c = conn + 10 * e;
+        for (int i = 0; i < 10; ++i)
+            if (c[i] < 0 || c[i] >= N) return fmt("element %lld references node %d out of range", (long long)e, c[i]);
+        if (elem_mat[e] < 0 || elem_mat[e] >= n_mat) return fmt("element %lld has material %d out of range", (long long)e, elem_mat[e]);
+        const double* x0 = X + 3 * (int64_t)c[0];
+        double J[3][3];
+        double h2 = 0;
+        for (int k = 0; k < 3; ++k)
+            for (int r = 0; r < 3; ++r) {
+                J[r][k] = X[3 * (int64_t)c[k + 1] + r] - x0[r];
+                h2 = std::max(h2, std::fabs(J[r][k]));
+            }
+        double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        if (!(det > 1e-12 * h2 * h2 * h2)) return fmt("element %lld is inverted or degenerate", (long long)e);
+        for (int m = 0; m < 6; ++m) {
+            const double* xa = X + 3 * (int64_t)c[kEdge[m][0]];
+            const double* xb = X + 3 * (int64_t)c[kEdge[m][1]];
+            const double* xm = X + 3 * (int64_t)c[4 + m];
+            for (int r = 0; r < 3; ++r)
+                if (std::fabs(xm[r] - 0.5 * (xa[r] + xb[r])) > 1e-9 * h2)
+                    return fmt("element %lld: edge node %d is not at its edge midpoint", (long long)e, c[4 + m]);
+        }
+        for (int i = 0; i < 4; ++i) role[c[i]] |= 1;
+        for (int i = 4; i < 10; ++i) role[c[i]] |= 2;
+    }
+    for (int64_t v = 0; v < N; ++v) {
+        if (role[v] == 0) return fmt("node %lld is not used by any element", (long long)v);
+        if (role[v] == 3) return fmt("node %lld is a vertex of one element and an edge node of another", (long long)v);
+    }
+
+    // ---- Morton codes of nodes
+    Box box;
+    for (int d = 0; d < 3; ++d) { box.lo[d] = 1e300; box.hi[d] = -1e300; }
+    for (int64_t v = 0; v < N; ++v)
+        for (int d = 0; d < 3; ++d) {
+            box.lo[d] = std::min(box.lo[d], X[3 * v + d]);
+            box.hi[d] = std::max(box.hi[d], X[3 * v + d]);
+        }
+    std::vector<uint64_t> mort(N);
+    for (int64_t v = 0; v < N; ++v) mort[v] = box.morton(X + 3 * v);
+
+    // ---- regions
+    T.region_user.assign(N, 0);
+    if (region_of_node) {
+        int32_t rmax = -1;
+        for (int64_t v = 0; v < N; ++v) {
+            if (region_of_node[v] < 0) return "region ids must be non-negative";
+            rmax = std::max(rmax, region_of_node[v]);
+        }
+        T.n_regions = rmax + 1;
+        std::vector<int64_t> cnt(T.n_regions, 0);
+        for (int64_t v = 0; v < N; ++v) cnt[region_of_node[v]]++;
+        for (int32_t r = 0; r < T.n_regions; ++r)
+            if (cnt[r] == 0) return fmt("region %d is empty (ids must be dense)", r);
+        std::copy(region_of_node, region_of_node + N, T.region_user.begin());
+    } else {
+        if (region_nodes <= 0) region_nodes = 512;
+        std::vector<int32_t> ord(N);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return mort[a] < mort[b]; });
+        int64_t nr = (N + region_nodes - 1) / region_nodes;
+        T.n_regions = (int32_t)nr;
+        for (int64_t k = 0; k < N; ++k) T.region_user[ord[k]] = (int32_t)std::min<int64_t>(k / region_nodes, nr - 1);
+    }
+
+    // ---- internal node order: (region, Morton)
+    T.i2u.resize(N);
+    std::iota(T.i2u.begin(), T.i2u.end(), 0);
+    std::stable_sort(T.i2u.begin(), T.i2u.end(), [&](int32_t a, int32_t b) {
+        if (T.region_user[a] != T.region_user[b]) return T.region_user[a] < T.region_user[b];
+        return mort[a] < mort[b];
+    });
+    T.u2i.resize(N);
+    for (int64_t i = 0; i < N; ++i) T.u2i[T.i2u[i]] = (int32_t)i;
+    T.region_start.assign(T.n_regions + 1, 0);
+    for (int64_t v = 0; v < N; ++v) T.region_start[T.region_user[v] + 1]++;
+    for (int32_t r = 0; r < T.n_regions; ++r) T.region_start[r + 1] += T.region_start[r];
+    T.coords.resize(3 * N);
+    T.fixmask.resize(N);
+    for (int64_t i = 0; i < N; ++i) {
+        int32_t u = T.i2u[i];
+        for (int d = 0; d < 3; ++d) T.coords[3 * i + d] = X[3 * (int64_t)u + d];
+        T.fixmask[i] = (uint8_t)((fixed[3 * (int64_t)u] ? 1 : 0) | (fixed[3 * (int64_t)u + 1] ? 2 : 0) |
+                                 (fixed[3 * (int64_t)u + 2] ? 4 : 0));
+    }
+
+    // ---- element order
+    std::vector<int32_t> eord(E);
+    std::iota(eord.begin(), eord.end(), 0);
+    std::vector<int32_t> ekey(E);
+    std::vector<uint64_t> emort(E);
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t* c = conn + 10 * e;
+        int32_t k = INT32_MAX;
+        double cen[3] = {0, 0, 0};
+        for (int i = 0; i < 4; ++i) {
+            k = std::min(k, T.u2i[c[i]]);
+            for (int d = 0; d < 3; ++d) cen[d] += 0.25 * X[3 * (int64_t)c[i] + d];
+        }
+        ekey[e] = k;
+        emort[e] = box.morton(cen);
+    }
+    std::stable_sort(eord.begin(), eord.end(), [&](int32_t a, int32_t b) {
+        if (ekey[a] != ekey[b]) return ekey[a] < ekey[b];
+        return emort[a] < emort[b];
+    });
+
+    // ---- patches
+    int64_t P = (E + patch_elems - 1) / patch_elems;
+    int64_t Ppad = (P + 7) / 8 * 8;
+    T.n_patches = (int32_t)P;
+    T.n_patches_pad = (int32_t)Ppad;
+    T.patch_el_ptr.assign(Ppad + 1, 0);
+    T.patch_pn_ptr.assign(Ppad + 1, 0);
+    T.patch_nv.assign(Ppad, 0);
+    T.elems.resize(E);
+    T.patch_nodes.clear();
+    T.patch_nodes.reserve(3 * N);
+    std::vector<int32_t> nodes;
+    std::vector<int32_t> local(N, -1);
+    std::vector<uint8_t> seen(N, 0);
+    for (int64_t p = 0; p < Ppad; ++p) {
+        int64_t e0 = std::min<int64_t>(p * patch_elems, E), e1 = std::min<int64_t>(e0 + patch_elems, E);
+        T.patch_el_ptr[p + 1] = (int32_t)e1;
+        nodes.clear();
+        for (int64_t k = e0; k < e1; ++k) {
+            const int32_t* c = conn + 10 * (int64_t)eord[k];
+            for (int i = 0; i < 10; ++i) nodes.push_back(T.u2i[c[i]]);
+        }
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        // vertices first
+        std::stable_partition(nodes.begin(), nodes.end(), [&](int32_t v) { return role[T.i2u[v]] == 1; });
+        int nv = 0;
+        for (int32_t v : nodes) nv += role[T.i2u[v]] == 1;
+        if (nodes.size() > 65535) return "patch too large";
+        for (size_t j = 0; j < nodes.size(); ++j) {
+            int32_t v = nodes[j];
+            local[v] = (int32_t)j;
+            uint32_t ent = (uint32_t)v;
+            if (!seen[v]) { ent |= kOwnerBit; seen[v] = 1; }
+            T.patch_nodes.push_back(ent);
+        }
+        for (int64_t k = e0; k < e1; ++k) {
+            const int32_t* c = conn + 10 * (int64_t)eord[k];
+            ElemRec& r = T.elems[k];
+            for (int i = 0; i < 10; ++i) r.lid[i] = (uint16_t)local[T.u2i[c[i]]];
+            r.mat = (uint16_t)elem_mat[eord[k]];
+            r.pad = 0;
+        }
+        T.patch_nv[p] = nv;
+        T.patch_pn_ptr[p + 1] = (int32_t)T.patch_nodes.size();
+        T.max_pn = std::max<int32_t>(T.max_pn, (int32_t)nodes.size());
+        T.max_nv = std::max(T.max_nv, nv);
+    }
+    if ((int64_t)T.patch_nodes.size() >= ((int64_t)1 << 31)) return "too many patch nodes";
+
+    // ---- per-node slot lists (patch order)
+    T.node_pn_ptr.assign(N + 1, 0);
+    for (uint32_t ent : T.patch_nodes) T.node_pn_ptr[(ent & ~kOwnerBit) + 1]++;
+    for (int64_t v = 0; v < N; ++v) T.node_pn_ptr[v + 1] += T.node_pn_ptr[v];
+    T.node_pn.resize(T.patch_nodes.size());
+    std::vector<int32_t> pos(T.node_pn_ptr.begin(), T.node_pn_ptr.end() - 1);
+    for (size_t k = 0; k < T.patch_nodes.size(); ++k) T.node_pn[pos[T.patch_nodes[k] & ~kOwnerBit]++] = (int32_t)k;
+    for (int64_t v = 0; v < N; ++v)
+        if (T.node_pn_ptr[v + 1] == T.node_pn_ptr[v]) return "internal error: node without patch";
+    return std::string();
+}
+
+}  // namespace ebe

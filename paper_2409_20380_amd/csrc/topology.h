@@ -1,0 +1,55 @@
+// topology.h -- host-side mesh preprocessing for the element-by-element
+// kernels: internal node order, element patches, patch-local numbering and
+// the per-node list of patch slots that the matvec writes.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ebe {
+
+// Bit set on a patch-node entry when that patch is the first (owner) patch of
+// the node: the owner writes per-node values that every touching patch computes.
+constexpr uint32_t kOwnerBit = 0x80000000u;
+constexpr int kMaxPatchElems = 64;   // one element per lane of a 64-wide wavefront
+
+// Element record used by the kernels: ten patch-local node indices (vertices
+// first, then edges in the conn order), the material id and one pad word.
+struct ElemRec {
+    uint16_t lid[10];
+    uint16_t mat;
+    uint16_t pad;
+};
+static_assert(sizeof(ElemRec) == 24, "ElemRec must be 24 bytes");
+
+struct Topology {
+    int64_t n_nodes = 0, n_elems = 0;
+    int32_t n_regions = 0;
+    // node numbering
+    std::vector<int32_t> i2u, u2i;          // internal -> user, user -> internal
+    std::vector<int32_t> region_user;       // region id per user node
+    std::vector<int32_t> region_start;      // [n_regions+1] internal node ranges
+    std::vector<double> coords;             // [N][3] internal order
+    std::vector<uint8_t> fixmask;           // [N] bit c = component c fixed, internal order
+    // patches
+    int32_t n_patches = 0, n_patches_pad = 0;   // pad = multiple of 8 (XCD count)
+    std::vector<int32_t> patch_el_ptr;      // [Ppad+1] element ranges (internal element order)
+    std::vector<int32_t> patch_pn_ptr;      // [Ppad+1] patch-node ranges
+    std::vector<int32_t> patch_nv;          // [Ppad] number of vertex nodes (local ids < nv)
+    std::vector<uint32_t> patch_nodes;      // [PN] internal node id | kOwnerBit
+    std::vector<ElemRec> elems;             // [E] internal element order
+    int32_t max_pn = 0, max_nv = 0;
+    // per node: patch-node slots it receives contributions from (in patch order)
+    std::vector<int32_t> node_pn_ptr;       // [N+1]
+    std::vector<int32_t> node_pn;           // [PN]
+    // material table: lambda, mu, rho
+    std::vector<double> mat_lmr;
+};
+
+// Builds the topology; returns an empty string on success or an error message.
+std::string build_topology(Topology& T, int64_t n_nodes, const double* coords, int64_t n_elems,
+                           const int32_t* conn, const int32_t* elem_mat, int32_t n_mat, const double* mat,
+                           const uint8_t* fixed, const int32_t* region_of_node, int region_nodes,
+                           int patch_elems);
+
+}  // namespace ebe

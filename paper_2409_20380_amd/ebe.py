@@ -1,0 +1,266 @@
+"""Thin ctypes binding of the C ABI declared in ``include/ebe.h``.
+
+Argument marshalling only: every numerical step runs in the gfx950 kernels of
+``libebe.so``.  Device vectors are torch float64 CUDA tensors (contiguous,
+length 3 * n_nodes, node-major xyz); PyTorch provides device memory and the
+stream.  There is no CPU fallback: if the library is missing the import of
+this module's ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libebe.so")
+
+OK, NOT_CONVERGED = 0, 1
+E_INVALID_ARG, E_HIP, E_NO_MEMORY, E_BAD_STATE, E_NONFINITE = -1, -2, -3, -4, -5
+PRED_ZERO, PRED_AB4, PRED_SNAPSHOT = 0, 1, 2
+
+
+class EbeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ebe error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("dt", C.c_double), ("rayleigh_alpha", C.c_double), ("rayleigh_beta", C.c_double),
+                ("tol", C.c_double), ("drop_tol", C.c_double), ("max_iter", C.c_int32), ("s", C.c_int32),
+                ("predictor", C.c_int32), ("region_nodes", C.c_int32), ("patch_elems", C.c_int32),
+                ("chunk_iters", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("pad", C.c_int32),
+                ("res0", C.c_double), ("res_rec", C.c_double), ("res_true", C.c_double), ("bnorm", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("it", C.c_int32), ("s_eff", C.c_int32), ("iters", C.c_int32), ("restarts", C.c_int32),
+                ("status", C.c_int32), ("pad", C.c_int32), ("res0", C.c_double), ("res_rec", C.c_double),
+                ("res_true", C.c_double), ("bnorm", C.c_double)]
+
+
+# Every symbol include/ebe.h declares (checked by the CPU test suite).
+EXPORTS = ("ebe_version", "ebe_create", "ebe_destroy", "ebe_last_error", "ebe_assemble", "ebe_get_regions",
+           "ebe_apply", "ebe_apply_mk", "ebe_precond", "ebe_rhs", "ebe_predict", "ebe_refine", "ebe_step",
+           "ebe_get_state", "ebe_set_state", "ebe_get_history", "ebe_set_history", "ebe_sync",
+           "ebe_set_kernel_timing", "ebe_kernel_time", "ebe_sizes")
+
+_lib = None
+vp = C.c_void_p
+d_p = C.POINTER(C.c_double)
+i32_p = C.POINTER(C.c_int32)
+i64_p = C.POINTER(C.c_int64)
+u8_p = C.POINTER(C.c_uint8)
+
+
+def lib():
+    """Load libebe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2409_20380_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    L.ebe_version.restype = C.c_char_p
+    L.ebe_last_error.restype = C.c_char_p
+    L.ebe_last_error.argtypes = [vp]
+    L.ebe_create.argtypes = [C.POINTER(Config), vp, C.POINTER(vp)]
+    L.ebe_destroy.argtypes = [vp]
+    L.ebe_assemble.argtypes = [vp, C.c_int64, d_p, C.c_int64, i32_p, i32_p, C.c_int32, d_p, u8_p, i32_p]
+    L.ebe_get_regions.argtypes = [vp, i32_p, i32_p]
+    L.ebe_apply.argtypes = [vp, vp, vp]
+    L.ebe_apply_mk.argtypes = [vp, C.c_double, C.c_double, vp, vp]
+    L.ebe_precond.argtypes = [vp, vp, vp]
+    L.ebe_rhs.argtypes = [vp, vp, d_p, vp]
+    L.ebe_predict.argtypes = [vp, vp, vp, i32_p]
+    L.ebe_refine.argtypes = [vp, vp, vp, C.POINTER(SolveStats)]
+    L.ebe_step.argtypes = [vp, vp, d_p, C.POINTER(StepStats)]
+    L.ebe_get_state.argtypes = [vp, vp, vp, vp]
+    L.ebe_set_state.argtypes = [vp, vp, vp, vp]
+    L.ebe_get_history.argtypes = [vp, vp, vp, i32_p]
+    L.ebe_set_history.argtypes = [vp, vp, vp, C.c_int32]
+    L.ebe_sync.argtypes = [vp]
+    L.ebe_set_kernel_timing.argtypes = [vp, C.c_int32]
+    L.ebe_kernel_time.argtypes = [vp, i64_p, d_p]
+    L.ebe_sizes.argtypes = [vp, i64_p, i64_p, i64_p, i64_p]
+    for name in EXPORTS:
+        getattr(L, name).restype = getattr(L, name).restype or C.c_int
+    L.ebe_version.restype = C.c_char_p
+    L.ebe_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _dev(t):
+    """Device pointer of a contiguous float64 CUDA tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype, ptr_t):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(ptr_t)
+
+
+@dataclass
+class Mesh:
+    coords: np.ndarray
+    conn: np.ndarray
+    elem_mat: np.ndarray
+    mat: np.ndarray
+    fixed: np.ndarray
+    regions: np.ndarray | None = None
+
+
+class Solver:
+    """One handle of the library: a mesh, its state and its history."""
+
+    def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
+                 max_iter=10000, drop_tol=1e-6, region_nodes=512, patch_elems=64, chunk_iters=0, stream=None):
+        import torch
+        L = lib()
+        cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol,
+                     drop_tol=drop_tol, max_iter=max_iter, s=s, predictor=predictor, region_nodes=region_nodes,
+                     patch_elems=patch_elems, chunk_iters=chunk_iters)
+        self.cfg = cfg
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        rc = L.ebe_create(C.byref(cfg), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise EbeError(rc, L.ebe_last_error(None).decode())
+        self._h = h
+        self.n_nodes = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebe_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_not_converged=False):
+        if rc == OK or (allow_not_converged and rc == NOT_CONVERGED):
+            return rc
+        raise EbeError(rc, lib().ebe_last_error(self._h).decode())
+
+    @property
+    def n3(self):
+        return 3 * self.n_nodes
+
+    def assemble(self, coords, conn, elem_mat, mat, fixed, regions=None):
+        L = lib()
+        coords, cp = _host(coords, np.float64, d_p)
+        conn, np_ = _host(conn, np.int32, i32_p)
+        elem_mat, ep = _host(elem_mat, np.int32, i32_p)
+        mat, mp = _host(mat, np.float64, d_p)
+        fixed, fp = _host(fixed, np.uint8, u8_p)
+        rp = None
+        if regions is not None:
+            regions, rp = _host(regions, np.int32, i32_p)
+        self._check(L.ebe_assemble(self._h, coords.shape[0], cp, conn.shape[0], np_, ep, mat.shape[0], mp, fp, rp))
+        self.n_nodes = coords.shape[0]
+
+    def regions(self):
+        out = np.empty(self.n_nodes, dtype=np.int32)
+        n = C.c_int32()
+        self._check(lib().ebe_get_regions(self._h, out.ctypes.data_as(i32_p), C.byref(n)))
+        return out, n.value
+
+    def _out(self, out):
+        import torch
+        return torch.empty(self.n3, dtype=torch.float64, device="cuda") if out is None else out
+
+    def apply(self, p, out=None):
+        q = self._out(out)
+        self._check(lib().ebe_apply(self._h, _dev(p), _dev(q)))
+        return q
+
+    def apply_mk(self, cm, ck, p, out=None):
+        q = self._out(out)
+        self._check(lib().ebe_apply_mk(self._h, cm, ck, _dev(p), _dev(q)))
+        return q
+
+    def precond(self, r, out=None):
+        z = self._out(out)
+        self._check(lib().ebe_precond(self._h, _dev(r), _dev(z)))
+        return z
+
+    def rhs(self, f_ext=None, base_acc=None, out=None):
+        b = self._out(out)
+        g = None if base_acc is None else (C.c_double * 3)(*[float(x) for x in base_acc])
+        self._check(lib().ebe_rhs(self._h, _dev(f_ext), g, _dev(b)))
+        return b
+
+    def predict(self, f_next=None, out=None):
+        x = self._out(out)
+        se = C.c_int32()
+        self._check(lib().ebe_predict(self._h, _dev(f_next), _dev(x), C.byref(se)))
+        return x, se.value
+
+    def refine(self, b, x):
+        st = SolveStats()
+        rc = lib().ebe_refine(self._h, _dev(b), _dev(x), C.byref(st))
+        self._check(rc, allow_not_converged=True)
+        return st
+
+    def step(self, f_ext=None, base_acc=None, stats=True):
+        st = StepStats() if stats else None
+        g = None if base_acc is None else (C.c_double * 3)(*[float(x) for x in base_acc])
+        rc = lib().ebe_step(self._h, _dev(f_ext), g, C.byref(st) if stats else None)
+        self._check(rc, allow_not_converged=True)
+        return st
+
+    def get_state(self):
+        import torch
+        u, v, a = (torch.empty(self.n3, dtype=torch.float64, device="cuda") for _ in range(3))
+        self._check(lib().ebe_get_state(self._h, _dev(u), _dev(v), _dev(a)))
+        return u, v, a
+
+    def set_state(self, u=None, v=None, a=None):
+        self._check(lib().ebe_set_state(self._h, _dev(u), _dev(v), _dev(a)))
+
+    def get_history(self):
+        import torch
+        vh = torch.empty(4 * self.n3, dtype=torch.float64, device="cuda")
+        ring = torch.empty((self.cfg.s + 1) * self.n3, dtype=torch.float64, device="cuda")
+        it = C.c_int32()
+        self._check(lib().ebe_get_history(self._h, _dev(vh), _dev(ring), C.byref(it)))
+        return vh.view(4, self.n3), ring.view(self.cfg.s + 1, self.n3), it.value
+
+    def set_history(self, vhist, ring, it):
+        self._check(lib().ebe_set_history(self._h, _dev(vhist.contiguous().view(-1)),
+                                          _dev(ring.contiguous().view(-1)), int(it)))
+
+    def sync(self):
+        self._check(lib().ebe_sync(self._h))
+
+    def set_kernel_timing(self, every_n):
+        self._check(lib().ebe_set_kernel_timing(self._h, int(every_n)))
+
+    def kernel_time(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        self._check(lib().ebe_kernel_time(self._h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def sizes(self):
+        v = [C.c_int64() for _ in range(4)]
+        self._check(lib().ebe_sizes(self._h, *[C.byref(x) for x in v]))
+        return dict(n_nodes=v[0].value, n_elems=v[1].value, n_patch_nodes=v[2].value, n_patches=v[3].value)

@@ -72,9 +72,8 @@ struct ebe_handle {
     int last_iters = 0;
     DevScalars* sc = nullptr;
     DevScalars* sc_host = nullptr;
-    double* partial_pap = nullptr;
-    double* partial_upd = nullptr;
-    unsigned* counters = nullptr;
+    double* pap_part = nullptr;   // (p, A p) partials of the matvec grid
+    double* res_part = nullptr;   // two slots of [3][res_grid] residual partials
     // kernel timing
     int timing_every = 0;
     int64_t pcg_launches = 0;
@@ -200,17 +199,25 @@ void sync_stream(ebe_handle* h) {
 }
 
 // Algorithm 1 on internal-order vectors: b, x (guess in, solution out).
+// Trips are enqueued in chunks; a device-side stop flag makes the remaining
+// kernels of a chunk return at once, and the host reads the scalars once per
+// chunk.  Each chunk ends with the true-residual check, which only runs on the
+// device once the loop has stopped.
 int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
     hipStream_t s = h->stream;
     const double tol = h->cfg.tol;
     const int max_iter = h->cfg.max_iter;
+    const int g_res = res_grid(h->T.n_nodes);
+    const int g_pap = pcg_ebe_grid(h->dp);
+    auto slot = [&](int j) { return h->res_part + (size_t)(j & 1) * 3 * g_res; };
     launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
-    launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, h->partial_upd, h->counters + 1, 0, tol);
+    launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(0), 0);
     check_launch();
     int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters - 2);
     int done = DONE_RUNNING;
-    for (int guard = 0;; ++guard) {
-        for (int k = 0; k < chunk; ++k) {
+    int j = 0;
+    for (int round = 0;; ++round) {
+        for (int k = 0; k < chunk; ++k, ++j) {
             double* pprev = h->p[h->par];
             double* pcur = h->p[h->par ^ 1];
             bool timed = h->timing_every > 0 && (h->pcg_launches % h->timing_every) == 0;
@@ -220,30 +227,30 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
                 e1 = take_event(h);
                 HIPCHK(hipEventRecord(e0, s));
             }
-            launch_ebe_pcg(s, h->dp, h->z, pprev, pcur, h->cM, h->cK, h->qbuf, h->sc, h->partial_pap, h->counters);
+            launch_ebe_pcg(s, h->dp, h->z, pprev, pcur, h->cM, h->cK, h->qbuf, h->sc, slot(j), g_res, h->pap_part,
+                           j, max_iter, tol);
             if (timed) {
                 HIPCHK(hipEventRecord(e1, s));
                 h->ev_pending.emplace_back(e0, e1);
             }
             h->pcg_launches++;
-            launch_pcg_update(s, h->dn, h->qbuf, pcur, h->binv6, x, h->r, h->z, h->sc, h->partial_upd,
-                              h->counters + 1, tol, max_iter);
+            launch_pcg_update(s, h->dn, h->qbuf, pcur, h->binv6, x, h->r, h->z, h->sc, h->pap_part, g_pap,
+                              slot(j + 1), j);
             h->par ^= 1;
         }
-        // true-residual check, runs on the device only once the loop stopped
+        // true-residual check (runs on the device only once the loop stopped)
         launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf, h->sc);
-        launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, h->partial_upd, h->counters + 1, 1,
-                        tol);
+        launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(j), 1);
+        launch_check_finalize(s, h->sc, slot(j), g_res, j, tol);
         check_launch();
         HIPCHK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
         sync_stream(h);
         done = h->sc_host->done;
         if (done == DONE_RUNNING) {
             chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters / 8);
-            if (guard > 100000) throw HipError{"PCG loop did not terminate"};
+            if (round > 100000) throw HipError{"PCG loop did not terminate"};
             continue;
         }
-        if ((done == DONE_CONVERGED || done == DONE_MAXITER) && !h->sc_host->checked) continue;
         break;
     }
     const DevScalars& S = *h->sc_host;
@@ -260,11 +267,11 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
         st->res_true = S.bnorm > 0 ? S.res_true : 0.0;
         st->status = (done == DONE_MAXITER) ? EBE_NOT_CONVERGED : EBE_OK;
     }
-    h->last_iters = S.iters;
     if (done == DONE_NONFINITE) {
         h->err = "non-finite value in the PCG iteration";
         return EBE_E_NONFINITE;
     }
+    h->last_iters = S.iters;
     if (done == DONE_MAXITER) {
         h->err = "PCG reached max_iter";
         return EBE_NOT_CONVERGED;
@@ -416,11 +423,9 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->t1 = h->alloc<double>(n3);
         h->coef = h->alloc<double>(32 * (size_t)T.n_regions);
         h->sc = h->alloc<DevScalars>(1);
-        h->partial_pap = h->alloc<double>(T.n_patches_pad);
-        h->partial_upd = h->alloc<double>(3 * (size_t)update_blocks(N));
-        h->counters = h->alloc<unsigned>(2);
+        h->pap_part = h->alloc<double>(pcg_ebe_grid(h->dp));
+        h->res_part = h->alloc<double>(2 * 3 * (size_t)res_grid(N));
         if (!h->sc_host) HIPCHK(hipHostMalloc((void**)&h->sc_host, sizeof(DevScalars), hipHostMallocDefault));
-        HIPCHK(hipMemsetAsync(h->counters, 0, 2 * sizeof(unsigned), s));
         HIPCHK(hipMemsetAsync(h->sc, 0, sizeof(DevScalars), s));
         // block-Jacobi inverse of A_bc
         launch_ebe_diag(s, h->dp, h->cM, h->cK, h->qbuf);

@@ -8,20 +8,20 @@
 
 namespace ebe {
 
-// Device-side scalars of one PCG solve (Algorithm 1).
+// Device-side scalars of one PCG solve (Algorithm 1).  Written by workgroup 0
+// of the kernel that decides them; read by later kernels and the host.
 struct DevScalars {
-    double rho;       // (z, r) of the current residual
-    double alpha;
-    double beta;      // 0 on the first trip of a CG cycle
+    double rho[2];    // (z, r) of trip j, stored in slot j & 1
     double bnorm;     // ||b||
-    double rr;        // ||r||^2 of the current recursive residual
+    double rr;        // ||r||^2 of the last residual tested
     double res0;      // relative residual of the initial guess
     double res_true;  // relative true residual at the last check
-    double pap;       // (p, A p) of the last trip
     int32_t done;     // 0 running, 1 converged, 2 non-finite, 3 iteration cap, 4 zero rhs
-    int32_t iters;
+    int32_t iters;    // PCG trips taken
     int32_t restarts;
     int32_t checked;  // true residual evaluated since the loop stopped
+    int32_t cycle_start;  // trip index at which the current CG cycle began (beta = 0 there)
+    int32_t pad;
 };
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_NONFINITE = 2, DONE_MAXITER = 3, DONE_ZERO_RHS = 4 };
@@ -58,10 +58,12 @@ struct ColPtrs {
 // guard: if non-NULL, the kernel runs only when a true-residual check is due.
 void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
                       double* qbuf, const DevScalars* guard = nullptr);
-// PCG matvec: p_cur = z + beta p_prev (beta from sc), qbuf = A_e p_cur, and the
-// grid-wide (p, A p) that yields alpha = rho / (p, A p) in sc.
+// PCG trip j, matvec part: stop test on the incoming residual partials, beta,
+// p_cur = z + beta p_prev, qbuf = A_e p_cur and (p, A p) partials.
+int pcg_ebe_grid(const DevPatches& P);
 void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const double* p_prev, double* p_cur,
-                    double cm, double ck, double* qbuf, DevScalars* sc, double* partial, unsigned* counter);
+                    double cm, double ck, double* qbuf, DevScalars* sc, const double* res_part, int g_res,
+                    double* pap_part, int j, int max_iter, double tol);
 // Right-hand side operands: M part w1 = a + c1 v - g, K part w2 = c2 v - u.
 void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const double* v, const double* a,
                     double c1, double c2, double g0, double g1, double g2, double* qbuf);
@@ -73,15 +75,16 @@ void launch_combine_apply(hipStream_t s, const DevNodes& N, const double* qbuf, 
 void launch_diag_finalize(hipStream_t s, const DevNodes& N, const double* qbuf6, double* binv6);
 void launch_precond(hipStream_t s, const DevNodes& N, const double* binv6, const double* r, double* z);
 void launch_rhs_finalize(hipStream_t s, const DevNodes& N, const double* qbuf, const double* f_ext, double* b);
-// mode 0: initial residual (also sets x = b on fixed dofs); mode 1: true-residual
-// check, runs only when due (loop stopped and not yet checked)
+// Grid of the node-wise reduction kernels (their partial-sum count).
+int res_grid(int64_t n);
+// mode 0: initial residual of a solve (also sets x = b on fixed dofs, resets
+// the scalars); mode 1: true-residual check, runs only when due.
 void launch_residual(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, const double* binv6,
-                     double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter, int mode,
-                     double tol);
+                     double* x, double* r, double* z, DevScalars* sc, double* res_part, int mode);
+void launch_check_finalize(hipStream_t s, DevScalars* sc, const double* res_part, int g, int j_next, double tol);
 void launch_pcg_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, const double* binv6,
-                       double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter,
-                       double tol, int max_iter);
-int update_blocks(int64_t n);
+                       double* x, double* r, double* z, DevScalars* sc, const double* pap_part, int g_pap,
+                       double* res_part, int j);
 
 // ---- predictor and time integration (all lengths in dofs, 3N)
 void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const double* v2, const double* v3,

@@ -182,9 +182,7 @@ struct EbeArgs {
     double c1, c2;       // RHS: w1 = a + c1 v - g, w2 = c2 v - u
     double g0, g1, g2;
     int mask_in;         // APPLY
-    DevScalars* sc;      // PCG; APPLY: optional guard (run only when a residual check is due)
-    double* partial;     // PCG
-    unsigned* counter;   // PCG
+    const DevScalars* guard;  // APPLY: run only when a true-residual check is due
 };
 
 // True-residual check is due when the loop stopped (converged or capped) and
@@ -193,14 +191,11 @@ __device__ __forceinline__ bool check_due(const DevScalars* sc) {
     return (sc->done == DONE_CONVERGED || sc->done == DONE_MAXITER) && !sc->checked;
 }
 
+// One patch on one wavefront.  Returns this lane's share of (p, A p) (PCG).
 template <int MODE>
-__global__ __launch_bounds__(64) void k_ebe(EbeArgs A) {
-    if (MODE == MODE_PCG && A.sc->done) return;
-    if (MODE == MODE_APPLY && A.sc && !check_due(A.sc)) return;
-    extern __shared__ double lds[];
+__device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double beta, double* lds) {
     const DevPatches& P = A.P;
-    const int lane = threadIdx.x;
-    const int patch = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
     const int pn0 = P.pn_ptr[patch], npn = P.pn_ptr[patch + 1] - pn0;
     const int nv = P.nv[patch];
     const int e0 = P.el_ptr[patch], ne = P.el_ptr[patch + 1] - e0;
@@ -208,9 +203,6 @@ __global__ __launch_bounds__(64) void k_ebe(EbeArgs A) {
     double* lk = lm + 3 * P.max_pn;            // [max_pn][3] stiffness operand (RHS only)
     double* la = lk + (MODE == MODE_RHS ? 3 * P.max_pn : 0);   // [max_pn][3] accumulator
     double* lx = la + 3 * P.max_pn;            // [max_nv][3] vertex coordinates
-
-    double beta = 0.0;
-    if (MODE == MODE_PCG) beta = A.sc->beta;
 
     for (int j = lane; j < npn; j += 64) {
         uint32_t ent = P.nodes[pn0 + j];
@@ -293,54 +285,132 @@ __global__ __launch_bounds__(64) void k_ebe(EbeArgs A) {
         double* q = A.qbuf + 3 * (int64_t)(pn0 + j);
         q[0] = la[3 * j]; q[1] = la[3 * j + 1]; q[2] = la[3 * j + 2];
     }
+    __syncthreads();   // LDS is reused by the next patch of a persistent wave
+    return pap;
+}
 
-    if (MODE == MODE_PCG) {
-        pap = wave_sum(pap);
-        __shared__ int is_last;
-        if (lane == 0) {
-            A.partial[patch] = pap;
-            __threadfence();
-            unsigned t = __hip_atomic_fetch_add(A.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            is_last = (t == gridDim.x - 1);
-        }
-        __syncthreads();
-        if (is_last) {
-            __threadfence();
-            double s = 0.0;
-            for (int i = lane; i < (int)gridDim.x; i += 64)
-                s += __hip_atomic_load(A.partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s = wave_sum(s);
-            if (lane == 0) {
-                DevScalars* sc = A.sc;
-                sc->pap = s;
-                double alpha = sc->rho / s;
-                sc->alpha = alpha;
-                if (!isfinite(alpha)) sc->done = DONE_NONFINITE;
-                *A.counter = 0u;
-                __threadfence();
-            }
-        }
-    }
+template <int MODE>
+__global__ __launch_bounds__(64) void k_ebe(EbeArgs A) {
+    if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
+    extern __shared__ double lds[];
+    const int patch = xcd_remap(blockIdx.x, gridDim.x);
+    ebe_patch<MODE>(A, patch, 0.0, lds);
 }
 
 static size_t ebe_lds_bytes(const DevPatches& P, int mode) {
     return sizeof(double) * (size_t)(3 * P.max_pn * (mode == MODE_RHS ? 3 : 2) + 3 * P.max_nv);
 }
 
+// ---------------------------------------------------------------------------
+// PCG iteration kernels (Algorithm 1)
+// ---------------------------------------------------------------------------
+// Grid-wide scalars without atomics or device-scope fences: each kernel writes
+// one partial sum per workgroup with plain stores, and every workgroup of the
+// next kernel sums all partials in the same fixed order (the kernel boundary
+// makes them visible), so alpha, beta and the stop test are bitwise identical
+// in every workgroup.  Workgroup 0 records the scalars for later kernels and
+// the host.  Partial slots are double-buffered by iteration parity.
+
+struct PcgEbeArgs {
+    EbeArgs E;
+    DevScalars* sc;
+    const double* res_part;   // [3][g_res] (z,r), (r,r), (b,b) of the residual entering trip j
+    int g_res;
+    double* pap_part;         // [gridDim.x] (p, A p) partials written here
+    int j;                    // trip index within the solve (0-based)
+    int max_iter;
+    double tol;
+};
+
+// Trip j of Algorithm 1, matvec part: stop test on the incoming residual,
+// beta = rho_j / rho_{j-1} (0 on the first trip of a cycle), p = z + beta p,
+// q = A p (patch slots) and the partials of (p, A p).  Persistent grid: each
+// workgroup walks a contiguous (per XCD) range of patches.
+__global__ __launch_bounds__(64) void k_ebe_pcg(PcgEbeArgs A) {
+    DevScalars* sc = A.sc;
+    if (sc->done) return;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int j = A.j;
+    double zr = 0.0, rr = 0.0, bb = 0.0;
+    for (int i = lane; i < A.g_res; i += 64) {
+        zr += A.res_part[i];
+        rr += A.res_part[A.g_res + i];
+        if (j == 0) bb += A.res_part[2 * A.g_res + i];
+    }
+    zr = wave_sum(zr);
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    const double bnorm = (j == 0) ? sqrt(bb) : sc->bnorm;
+    const double res = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+    int stop = DONE_RUNNING;
+    if (bnorm == 0.0) stop = DONE_ZERO_RHS;
+    else if (!isfinite(res) || !isfinite(zr)) stop = DONE_NONFINITE;
+    else if (res < A.tol) stop = DONE_CONVERGED;
+    else if (j >= A.max_iter) stop = DONE_MAXITER;
+    double beta = 0.0;
+    if (stop == DONE_RUNNING && j != sc->cycle_start) {
+        beta = zr / sc->rho[(j - 1) & 1];
+        if (!isfinite(beta)) stop = DONE_NONFINITE;
+    }
+    if (blockIdx.x == 0 && lane == 0) {
+        if (j == 0) {
+            sc->bnorm = bnorm;
+            sc->res0 = res;
+        }
+        sc->rr = rr;
+        if (stop != DONE_RUNNING) {
+            sc->done = stop;
+            sc->iters = j;
+        } else {
+            sc->rho[j & 1] = zr;
+            sc->iters = j + 1;
+        }
+    }
+    if (stop != DONE_RUNNING) return;
+
+    const int nb = gridDim.x;              // multiple of 8
+    const int xcd = blockIdx.x & 7, k0 = blockIdx.x >> 3, per_xcd_wg = nb >> 3;
+    const int chunk = A.E.P.n_patches_pad >> 3;
+    double pap = 0.0;
+    for (int k = k0; k < chunk; k += per_xcd_wg) pap += ebe_patch<MODE_PCG>(A.E, xcd * chunk + k, beta, lds);
+    pap = wave_sum(pap);
+    if (lane == 0) A.pap_part[blockIdx.x] = pap;
+}
+
+__device__ __forceinline__ double block_bcast_sum(double v) {
+    __shared__ double red[4];
+    __shared__ double out;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) out = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return out;
+}
+
 void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
                       double* qbuf, const DevScalars* guard) {
     EbeArgs A{};
     A.P = P; A.in0 = p; A.qbuf = qbuf; A.cm = cm; A.ck = ck; A.mask_in = mask_in ? 1 : 0;
-    A.sc = const_cast<DevScalars*>(guard);
+    A.guard = guard;
     hipLaunchKernelGGL(k_ebe<MODE_APPLY>, dim3(P.n_patches_pad), dim3(64), ebe_lds_bytes(P, MODE_APPLY), s, A);
 }
 
+int pcg_ebe_grid(const DevPatches& P) {
+    int g = P.n_patches_pad < 2048 ? P.n_patches_pad : 2048;
+    return g;   // n_patches_pad is a multiple of 8, so is g
+}
+
 void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const double* p_prev, double* p_cur,
-                    double cm, double ck, double* qbuf, DevScalars* sc, double* partial, unsigned* counter) {
-    EbeArgs A{};
-    A.P = P; A.in0 = z; A.in1 = p_prev; A.p_cur = p_cur; A.qbuf = qbuf; A.cm = cm; A.ck = ck;
-    A.sc = sc; A.partial = partial; A.counter = counter;
-    hipLaunchKernelGGL(k_ebe<MODE_PCG>, dim3(P.n_patches_pad), dim3(64), ebe_lds_bytes(P, MODE_PCG), s, A);
+                    double cm, double ck, double* qbuf, DevScalars* sc, const double* res_part, int g_res,
+                    double* pap_part, int j, int max_iter, double tol) {
+    PcgEbeArgs A{};
+    A.E.P = P; A.E.in0 = z; A.E.in1 = p_prev; A.E.p_cur = p_cur; A.E.qbuf = qbuf; A.E.cm = cm; A.E.ck = ck;
+    A.sc = sc; A.res_part = res_part; A.g_res = g_res; A.pap_part = pap_part; A.j = j; A.max_iter = max_iter;
+    A.tol = tol;
+    hipLaunchKernelGGL(k_ebe_pcg, dim3(pcg_ebe_grid(P)), dim3(64), ebe_lds_bytes(P, MODE_PCG), s, A);
 }
 
 void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const double* v, const double* a,
@@ -523,62 +593,29 @@ void launch_rhs_finalize(hipStream_t s, const DevNodes& N, const double* qbuf, c
     hipLaunchKernelGGL(k_rhs_finalize, dim3(nb), dim3(256), 0, s, N, qbuf, f_ext, b);
 }
 
-// Deterministic block reduction of NV values over 256 threads; result valid in thread 0.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV]) {
-    __shared__ double red[4][NV];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int t = 0; t < NV; ++t) v[t] = wave_sum(v[t]);
-    if (lane == 0)
-#pragma unroll
-        for (int t = 0; t < NV; ++t) red[w][t] = v[t];
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int t = 0; t < NV; ++t) v[t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+int res_grid(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)(g < 512 ? g : 512);
 }
 
-// Last-block epilogue: sum NV partial arrays (stride gridDim.x) in fixed order.
-template <int NV>
-__device__ __forceinline__ bool last_block_sum(const double (&v)[NV], double* partial, unsigned* counter,
-                                               double (&tot)[NV]) {
-    __shared__ int is_last;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int t = 0; t < NV; ++t) partial[t * gridDim.x + blockIdx.x] = v[t];
-        __threadfence();
-        unsigned k = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (k == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double s[NV];
-#pragma unroll
-    for (int t = 0; t < NV; ++t) s[t] = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
-#pragma unroll
-        for (int t = 0; t < NV; ++t)
-            s[t] += __hip_atomic_load(partial + t * gridDim.x + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    block_sum<NV>(s);
-#pragma unroll
-    for (int t = 0; t < NV; ++t) tot[t] = s[t];
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
-}
-
-// r = b - A x (from the slots), z = B^{-1} r, and (z,r), (r,r), (b,b).
-// mode 0 (initial): sets bnorm, res0, rho, beta = 0, iters = 0, done.
-// mode 1 (true-residual check): sets res_true; restarts the cycle when it
-// is not below tol (rho = (z,r), beta = 0, done = 0).
+// r = b - A x (from the slots), z = B^{-1} r; partials of (z,r), (r,r), (b,b)
+// into res_part[3][gridDim.x].  mode 0 (start of a solve): also x = b on fixed
+// dofs and resets the solve scalars.  mode 1 (true-residual check): runs only
+// when the check is due, the scalars are finished by k_check_finalize.
 __global__ __launch_bounds__(256) void k_residual(DevNodes N, const double* qbuf, const double* b, const double* binv6,
-                                                  double* x, double* r, double* z, DevScalars* sc, double* partial,
-                                                  unsigned* counter, int mode, double tol) {
+                                                  double* x, double* r, double* z, DevScalars* sc,
+                                                  double* res_part, int mode) {
     if (mode == 1 && !check_due(sc)) return;
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (n < N.n) {
+    if (mode == 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->done = DONE_RUNNING;
+        sc->iters = 0;
+        sc->restarts = 0;
+        sc->checked = 0;
+        sc->cycle_start = 0;
+        sc->res_true = 0.0;
+    }
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
         double q0, q1, q2;
         gather_q(N, qbuf, n, q0, q1, q2);
         uint8_t fm = N.fixmask[n];
@@ -595,67 +632,72 @@ __global__ __launch_bounds__(256) void k_residual(DevNodes N, const double* qbuf
         apply_binv(binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
         r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
         z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
-        v[0] = z0 * r0 + z1 * r1 + z2 * r2;
-        v[1] = r0 * r0 + r1 * r1 + r2 * r2;
-        v[2] = b0 * b0 + b1 * b1 + b2 * b2;
+        v0 += z0 * r0 + z1 * r1 + z2 * r2;
+        v1 += r0 * r0 + r1 * r1 + r2 * r2;
+        v2 += b0 * b0 + b1 * b1 + b2 * b2;
     }
-    block_sum<3>(v);
-    double tot[3];
-    if (last_block_sum<3>(v, partial, counter, tot) && threadIdx.x == 0) {
-        if (mode == 0) {
-            double bn = sqrt(tot[2]);
-            sc->bnorm = bn;
-            sc->rr = tot[1];
-            sc->rho = tot[0];
-            sc->beta = 0.0;
-            sc->iters = 0;
-            sc->restarts = 0;
-            sc->res_true = 0.0;
-            sc->checked = 0;
-            double res = bn > 0 ? sqrt(tot[1]) / bn : 0.0;
-            sc->res0 = res;
-            if (bn == 0.0) sc->done = DONE_ZERO_RHS;
-            else if (!isfinite(res) || !isfinite(tot[0])) sc->done = DONE_NONFINITE;
-            else sc->done = (res < tol) ? DONE_CONVERGED : DONE_RUNNING;
-        } else {
-            double res = sqrt(tot[1]) / sc->bnorm;
-            sc->res_true = res;
-            sc->checked = 1;
-            if (!isfinite(res)) sc->done = DONE_NONFINITE;
-            else if (res >= tol && sc->done == DONE_CONVERGED) {
-                sc->checked = 0;
-                sc->rr = tot[1];
-                sc->rho = tot[0];
-                sc->beta = 0.0;
-                sc->restarts += 1;
-                sc->done = DONE_RUNNING;
-            }
-        }
-        __threadfence();
+    v0 = block_bcast_sum(v0);
+    v1 = block_bcast_sum(v1);
+    v2 = block_bcast_sum(v2);
+    if (threadIdx.x == 0) {
+        res_part[blockIdx.x] = v0;
+        res_part[gridDim.x + blockIdx.x] = v1;
+        res_part[2 * gridDim.x + blockIdx.x] = v2;
     }
 }
 
 void launch_residual(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, const double* binv6,
-                     double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter, int mode,
-                     double tol) {
-    hipLaunchKernelGGL(k_residual, dim3(update_blocks(N.n)), dim3(256), 0, s, N, qbuf, b, binv6, x, r, z, sc, partial,
-                       counter, mode, tol);
+                     double* x, double* r, double* z, DevScalars* sc, double* res_part, int mode) {
+    hipLaunchKernelGGL(k_residual, dim3(res_grid(N.n)), dim3(256), 0, s, N, qbuf, b, binv6, x, r, z, sc, res_part,
+                       mode);
 }
 
-int update_blocks(int64_t n) { return (int)((n + 255) / 256); }
+// Finish the true-residual check (one workgroup): relative true residual; if
+// it is not below tol after the recursive residual converged, restart the CG
+// cycle from the true residual at trip j_next (beta = 0 there).
+__global__ __launch_bounds__(256) void k_check_finalize(DevScalars* sc, const double* res_part, int g, int j_next,
+                                                        double tol) {
+    if (!check_due(sc)) return;
+    double rr = 0.0;
+    for (int i = threadIdx.x; i < g; i += 256) rr += res_part[g + i];
+    rr = block_bcast_sum(rr);
+    if (threadIdx.x == 0) {
+        double res = sqrt(rr) / sc->bnorm;
+        sc->res_true = res;
+        sc->checked = 1;
+        if (!isfinite(res)) {
+            sc->done = DONE_NONFINITE;
+        } else if (res >= tol && sc->done == DONE_CONVERGED) {
+            sc->done = DONE_RUNNING;
+            sc->checked = 0;
+            sc->restarts += 1;
+            sc->cycle_start = j_next;
+        }
+    }
+}
 
-// One trip of Algorithm 1 after the matvec: r -= alpha q, x += alpha p,
-// z = B^{-1} r, then (z, r) and (r, r).  The last block applies the stop test
-// ||r|| / ||b|| < tol and forms beta = (z,r)_new / (z,r)_old.
+void launch_check_finalize(hipStream_t s, DevScalars* sc, const double* res_part, int g, int j_next, double tol) {
+    hipLaunchKernelGGL(k_check_finalize, dim3(1), dim3(256), 0, s, sc, res_part, g, j_next, tol);
+}
+
+// Trip j, update part: alpha = rho_j / (p, A p) from the matvec partials,
+// r -= alpha q, x += alpha p, z = B^{-1} r, and partials of (z, r), (r, r)
+// for trip j + 1.  Persistent grid-stride over nodes.
 __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qbuf, const double* p,
                                                     const double* binv6, double* x, double* r, double* z,
-                                                    DevScalars* sc, double* partial, unsigned* counter, double tol,
-                                                    int max_iter) {
+                                                    DevScalars* sc, const double* pap_part, int g_pap,
+                                                    double* res_part, int j) {
     if (sc->done) return;
-    const double alpha = sc->alpha;
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double v[2] = {0.0, 0.0};
-    if (n < N.n) {
+    double pap = 0.0;
+    for (int i = threadIdx.x; i < g_pap; i += 256) pap += pap_part[i];
+    pap = block_bcast_sum(pap);
+    const double alpha = sc->rho[j & 1] / pap;
+    if (!isfinite(alpha)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = DONE_NONFINITE;
+        return;
+    }
+    double v0 = 0.0, v1 = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
         double q0, q1, q2;
         gather_q(N, qbuf, n, q0, q1, q2);
         uint8_t fm = N.fixmask[n];
@@ -672,34 +714,22 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qb
         apply_binv(binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
         r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
         z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
-        v[0] = z0 * r0 + z1 * r1 + z2 * r2;
-        v[1] = r0 * r0 + r1 * r1 + r2 * r2;
+        v0 += z0 * r0 + z1 * r1 + z2 * r2;
+        v1 += r0 * r0 + r1 * r1 + r2 * r2;
     }
-    block_sum<2>(v);
-    double tot[2];
-    if (last_block_sum<2>(v, partial, counter, tot) && threadIdx.x == 0) {
-        sc->iters += 1;
-        sc->rr = tot[1];
-        double res = sqrt(tot[1]) / sc->bnorm;
-        if (!isfinite(res) || !isfinite(tot[0])) {
-            sc->done = DONE_NONFINITE;
-        } else if (res < tol) {
-            sc->done = DONE_CONVERGED;
-        } else if (sc->iters >= max_iter) {
-            sc->done = DONE_MAXITER;
-        } else {
-            sc->beta = tot[0] / sc->rho;
-            sc->rho = tot[0];
-        }
-        __threadfence();
+    v0 = block_bcast_sum(v0);
+    v1 = block_bcast_sum(v1);
+    if (threadIdx.x == 0) {
+        res_part[blockIdx.x] = v0;
+        res_part[gridDim.x + blockIdx.x] = v1;
     }
 }
 
 void launch_pcg_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, const double* binv6,
-                       double* x, double* r, double* z, DevScalars* sc, double* partial, unsigned* counter,
-                       double tol, int max_iter) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(update_blocks(N.n)), dim3(256), 0, s, N, qbuf, p, binv6, x, r, z, sc,
-                       partial, counter, tol, max_iter);
+                       double* x, double* r, double* z, DevScalars* sc, const double* pap_part, int g_pap,
+                       double* res_part, int j) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(res_grid(N.n)), dim3(256), 0, s, N, qbuf, p, binv6, x, r, z, sc, pap_part,
+                       g_pap, res_part, j);
 }
 
 // ---------------------------------------------------------------------------

@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.json"))
+    ap.add_argument("--patch-elems", type=int, default=128, help="elements per EBE patch (1..128)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the steps, copy a buffer of this many MiB device-to-device once (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -107,11 +110,20 @@ def main():
     dof = 3 * mesh.n_nodes
     log(f"mesh {wl.cells}: {mesh.n_nodes} nodes, {dof} dof, {mesh.n_elems} elements")
     aR, bR = wl.rayleigh
-    sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol)
+    sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems)
     t0 = time.time()
     sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
     sizes = sol.sizes()
     log(f"assembled in {time.time() - t0:.1f} s: {sizes}")
+
+    if args.copy_probe_mib > 0:
+        src = torch.ones(args.copy_probe_mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
 
     for it in range(1, args.warmup + 1):
         st = sol.step(base_acc=wave[it])

@@ -334,7 +334,7 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     if (!(c.dt > 0) || !(c.tol > 0) || c.s < 0 || c.s > 32 || c.predictor < 0 || c.predictor > 2 ||
         c.rayleigh_alpha < 0 || c.rayleigh_beta < 0 || c.patch_elems > kMaxPatchElems) {
         g_create_error = "invalid configuration (need dt > 0, tol > 0, 0 <= s <= 32, predictor in 0..2, "
-                         "non-negative damping, patch_elems <= 64)";
+                         "non-negative damping, patch_elems <= 128)";
         return EBE_E_INVALID_ARG;
     }
     if (c.max_iter <= 0) c.max_iter = 10000;
@@ -389,6 +389,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->dp.pn_ptr = h->upload(T.patch_pn_ptr);
         h->dp.nv = h->upload(T.patch_nv);
         h->dp.nodes = h->upload(T.patch_nodes);
+        h->dp.slot = h->upload(T.patch_slot);
         h->dp.elems = h->upload(T.elems);
         h->dp.coords = h->upload(T.coords);
         h->dp.mat = h->upload(T.mat_lmr);
@@ -397,8 +398,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->dp.n_patches_pad = T.n_patches_pad;
         h->dp.max_pn = T.max_pn;
         h->dp.max_nv = T.max_nv;
-        h->dn.pn_ptr = h->upload(T.node_pn_ptr);
-        h->dn.pn = h->upload(T.node_pn);
+        h->dn.slot_ptr = h->upload(T.slot_ptr);
         h->dn.fixmask = fm;
         h->dn.n = N;
         h->d_i2u = h->upload(T.i2u);

@@ -31,7 +31,8 @@ struct DevPatches {
     const int32_t* el_ptr;      // [Ppad+1]
     const int32_t* pn_ptr;      // [Ppad+1]
     const int32_t* nv;          // [Ppad]
-    const uint32_t* nodes;      // [PN]
+    const uint32_t* nodes;      // [PN] internal node id | owner bit
+    const int32_t* slot;        // [PN] output slot of each patch node
     const ElemRec* elems;       // [E]
     const double* coords;       // [N][3]
     const double* mat;          // [n_mat][3] lambda, mu, rho
@@ -41,13 +42,14 @@ struct DevPatches {
 };
 
 struct DevNodes {
-    const int32_t* pn_ptr;      // [N+1]
-    const int32_t* pn;          // [PN]
+    const int32_t* slot_ptr;    // [N+1] node n sums slots [slot_ptr[n], slot_ptr[n+1])
     const uint8_t* fixmask;     // [N]
     int64_t n;
 };
 
 constexpr int kMaxCols = 33;    // s <= 32 input columns plus the query
+constexpr int kMaxPcgGrid = 2048;   // persistent workgroups of the PCG matvec (multiple of 8)
+constexpr int kMaxResGrid = 1024;   // workgroups of the node-wise reduction kernels
 struct ColPtrs {
     const double* c[kMaxCols];
 };

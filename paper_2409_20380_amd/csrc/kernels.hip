@@ -48,6 +48,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return (bid & 7) * per + (bid >> 3);
 }
 
+// Sum of n partials p[0..n) as seen by one lane of nlanes: the lane loads its
+// strided share (at most PER values) all at once, then adds in a fixed order.
+template <int PER>
+__device__ __forceinline__ double lane_partials(const double* __restrict__ p, int n, int lane, int nlanes) {
+    double v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = lane + k * nlanes;
+        v[k] = i < n ? p[i] : 0.0;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) s += v[k];
+    return s;
+}
+
 __device__ __forceinline__ void lds_add(double* p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -166,6 +182,91 @@ __device__ __forceinline__ void element_apply(const double (&pm)[10][3], const d
     }
 }
 
+// Same operator as element_apply, with each node's 3-vector handed to
+// emit(i, f0, f1, f2) as soon as it is formed: the 30 outputs are never all
+// live, which keeps register pressure (and so occupancy) in check.
+template <class Emit>
+__device__ __forceinline__ void element_apply_emit(const double (&pm)[10][3], const double (&pk)[10][3], const Geo& G,
+                                                   double lamV, double muV, double mc, Emit&& emit) {
+    double sg[4][6];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (j == k) continue;
+            const int e = edge_of(k, j);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double d = 4.0 * pk[e][c] - pk[j][c] - 3.0 * pk[k][c];
+#pragma unroll
+                for (int dd = 0; dd < 3; ++dd) H[c][dd] = fma(d, G.g[j][dd], H[c][dd]);
+            }
+        }
+        double tr = lamV * (H[0][0] + H[1][1] + H[2][2]);
+        double m2 = 2.0 * muV;
+        sg[k][0] = fma(m2, H[0][0], tr);
+        sg[k][1] = fma(m2, H[1][1], tr);
+        sg[k][2] = fma(m2, H[2][2], tr);
+        sg[k][3] = muV * (H[0][1] + H[1][0]);
+        sg[k][4] = muV * (H[0][2] + H[2][0]);
+        sg[k][5] = muV * (H[1][2] + H[2][1]);
+    }
+    double S[6];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) S[t] = (sg[0][t] + sg[1][t]) + (sg[2][t] + sg[3][t]);
+    double Pv[3], Pe[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Pv[c] = (pm[0][c] + pm[1][c]) + (pm[2][c] + pm[3][c]);
+        Pe[c] = (pm[4][c] + pm[5][c]) + (pm[6][c] + pm[7][c]) + (pm[8][c] + pm[9][c]);
+    }
+    // vertices: stiffness (4 sigma_k - S) g_k, mass row 5 p_k + Pv - 6 Pe + 2 (incident edges)
+    constexpr int INC[4][3] = {{4, 6, 7}, {4, 5, 8}, {5, 6, 9}, {7, 8, 9}};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double t[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) t[q] = fma(4.0, sg[k][q], -S[q]);
+        const double* g = G.g[k];
+        double f[3];
+        f[0] = t[0] * g[0] + t[3] * g[1] + t[4] * g[2];
+        f[1] = t[3] * g[0] + t[1] * g[1] + t[5] * g[2];
+        f[2] = t[4] * g[0] + t[5] * g[1] + t[2] * g[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double m = fma(5.0, pm[k][c], Pv[c] - 6.0 * Pe[c]) + 2.0 * (pm[INC[k][0]][c] + pm[INC[k][1]][c] + pm[INC[k][2]][c]);
+            f[c] = fma(mc, m, f[c]);
+        }
+        emit(k, f[0], f[1], f[2]);
+    }
+    // edges (k, j): stiffness 4 ((sigma_k + S) g_j + (sigma_j + S) g_k),
+    // mass row -6 Pv + 2 (p_k + p_j) + 16 Pe + 16 p_e - 8 p_opposite
+    constexpr int EV[6][3] = {{0, 1, 9}, {1, 2, 7}, {0, 2, 8}, {0, 3, 5}, {1, 3, 6}, {2, 3, 4}};
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        const int k = EV[m][0], j = EV[m][1], o = EV[m][2];
+        const double* gj = G.g[j];
+        const double* gk = G.g[k];
+        double A[6], B[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            A[q] = 4.0 * (sg[k][q] + S[q]);
+            B[q] = 4.0 * (sg[j][q] + S[q]);
+        }
+        double f[3];
+        f[0] = A[0] * gj[0] + A[3] * gj[1] + A[4] * gj[2] + B[0] * gk[0] + B[3] * gk[1] + B[4] * gk[2];
+        f[1] = A[3] * gj[0] + A[1] * gj[1] + A[5] * gj[2] + B[3] * gk[0] + B[1] * gk[1] + B[5] * gk[2];
+        f[2] = A[4] * gj[0] + A[5] * gj[1] + A[2] * gj[2] + B[4] * gk[0] + B[5] * gk[1] + B[2] * gk[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double mm = fma(16.0, Pe[c], -6.0 * Pv[c]) + 2.0 * (pm[k][c] + pm[j][c]) + 16.0 * pm[4 + m][c] - 8.0 * pm[o][c];
+            f[c] = fma(mc, mm, f[c]);
+        }
+        emit(4 + m, f[0], f[1], f[2]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // element-by-element kernel (one wavefront per patch)
 // ---------------------------------------------------------------------------
@@ -204,61 +305,102 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     double* la = lk + (MODE == MODE_RHS ? 3 * P.max_pn : 0);   // [max_pn][3] accumulator
     double* lx = la + 3 * P.max_pn;            // [max_nv][3] vertex coordinates
 
-    for (int j = lane; j < npn; j += 64) {
-        uint32_t ent = P.nodes[pn0 + j];
-        int g = (int)(ent & ~kOwnerBit);
-        double v0, v1, v2;
-        if (MODE == MODE_APPLY) {
-            v0 = A.in0[3 * (int64_t)g]; v1 = A.in0[3 * (int64_t)g + 1]; v2 = A.in0[3 * (int64_t)g + 2];
-            if (A.mask_in) {
-                uint8_t fm = P.fixmask[g];
-                if (fm & 1) v0 = 0.0;
-                if (fm & 2) v1 = 0.0;
-                if (fm & 4) v2 = 0.0;
-            }
-        } else if (MODE == MODE_PCG) {
-            v0 = A.in0[3 * (int64_t)g]; v1 = A.in0[3 * (int64_t)g + 1]; v2 = A.in0[3 * (int64_t)g + 2];
-            if (beta != 0.0) {
-                v0 = fma(beta, A.in1[3 * (int64_t)g], v0);
-                v1 = fma(beta, A.in1[3 * (int64_t)g + 1], v1);
-                v2 = fma(beta, A.in1[3 * (int64_t)g + 2], v2);
-            }
-            if (ent & kOwnerBit) {
-                A.p_cur[3 * (int64_t)g] = v0; A.p_cur[3 * (int64_t)g + 1] = v1; A.p_cur[3 * (int64_t)g + 2] = v2;
-            }
-        } else {  // RHS
-            double u0 = A.in0[3 * (int64_t)g], u1 = A.in0[3 * (int64_t)g + 1], u2 = A.in0[3 * (int64_t)g + 2];
-            double w0 = A.in1[3 * (int64_t)g], w1 = A.in1[3 * (int64_t)g + 1], w2 = A.in1[3 * (int64_t)g + 2];
-            double a0 = A.in2[3 * (int64_t)g], a1 = A.in2[3 * (int64_t)g + 1], a2 = A.in2[3 * (int64_t)g + 2];
-            v0 = fma(A.c1, w0, a0) - A.g0; v1 = fma(A.c1, w1, a1) - A.g1; v2 = fma(A.c1, w2, a2) - A.g2;
-            lk[3 * j] = fma(A.c2, w0, -u0); lk[3 * j + 1] = fma(A.c2, w1, -u1); lk[3 * j + 2] = fma(A.c2, w2, -u2);
+    // Gather: the patch's node list is walked in groups of GU x 64 entries; all
+    // loads of a group are issued before any is consumed (memory-level
+    // parallelism instead of one dependent round trip per 64 nodes).
+    constexpr int GU = 4;
+    for (int jb = 0; jb < npn; jb += 64 * GU) {
+        uint32_t ent[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int j = jb + lane + 64 * u;
+            ent[u] = j < npn ? P.nodes[pn0 + j] : 0u;
         }
-        lm[3 * j] = v0; lm[3 * j + 1] = v1; lm[3 * j + 2] = v2;
-        la[3 * j] = 0.0; la[3 * j + 1] = 0.0; la[3 * j + 2] = 0.0;
-        if (j < nv) {
-            lx[3 * j] = P.coords[3 * (int64_t)g];
-            lx[3 * j + 1] = P.coords[3 * (int64_t)g + 1];
-            lx[3 * j + 2] = P.coords[3 * (int64_t)g + 2];
+        double v[GU][3], w[GU][3], xc[GU][3];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int j = jb + lane + 64 * u;
+            const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
+            const bool ok = j < npn;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                v[u][c] = ok ? A.in0[3 * g + c] : 0.0;
+                w[u][c] = (ok && (MODE == MODE_RHS || (MODE == MODE_PCG && beta != 0.0))) ? A.in1[3 * g + c] : 0.0;
+                xc[u][c] = (ok && j < nv) ? P.coords[3 * g + c] : 0.0;
+            }
+        }
+        double a3[GU][3];
+        if (MODE == MODE_RHS) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int j = jb + lane + 64 * u;
+                const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) a3[u][c] = j < npn ? A.in2[3 * g + c] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int j = jb + lane + 64 * u;
+            if (j >= npn) continue;
+            const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
+            double v0 = v[u][0], v1 = v[u][1], v2 = v[u][2];
+            if (MODE == MODE_APPLY) {
+                if (A.mask_in) {
+                    uint8_t fm = P.fixmask[g];
+                    if (fm & 1) v0 = 0.0;
+                    if (fm & 2) v1 = 0.0;
+                    if (fm & 4) v2 = 0.0;
+                }
+            } else if (MODE == MODE_PCG) {
+                v0 = fma(beta, w[u][0], v0);
+                v1 = fma(beta, w[u][1], v1);
+                v2 = fma(beta, w[u][2], v2);
+                if (ent[u] & kOwnerBit) {
+                    A.p_cur[3 * g] = v0; A.p_cur[3 * g + 1] = v1; A.p_cur[3 * g + 2] = v2;
+                }
+            } else {  // RHS: v = u, w = v (velocity), a3 = a
+                const double u0 = v0, u1 = v1, u2 = v2;
+                v0 = fma(A.c1, w[u][0], a3[u][0]) - A.g0;
+                v1 = fma(A.c1, w[u][1], a3[u][1]) - A.g1;
+                v2 = fma(A.c1, w[u][2], a3[u][2]) - A.g2;
+                lk[3 * j] = fma(A.c2, w[u][0], -u0);
+                lk[3 * j + 1] = fma(A.c2, w[u][1], -u1);
+                lk[3 * j + 2] = fma(A.c2, w[u][2], -u2);
+            }
+            lm[3 * j] = v0; lm[3 * j + 1] = v1; lm[3 * j + 2] = v2;
+            la[3 * j] = 0.0; la[3 * j + 1] = 0.0; la[3 * j + 2] = 0.0;
+            if (j < nv) {
+                lx[3 * j] = xc[u][0]; lx[3 * j + 1] = xc[u][1]; lx[3 * j + 2] = xc[u][2];
+            }
         }
     }
     __syncthreads();
 
     double pap = 0.0;
-    if (lane < ne) {
-        const ElemRec rec = P.elems[e0 + lane];
+#pragma unroll 1
+    for (int e = lane; e < ne; e += 64) {   // up to two elements per lane, in program order
+        const ElemRec rec = P.elems[e0 + e];
         Geo G;
         tet_geo(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
         const double* mp = P.mat + 3 * rec.mat;
         double w = G.V * (1.0 / 20.0) * A.ck;
         double lamV = mp[0] * w, muV = mp[1] * w;
         double mc = A.cm * mp[2] * G.V * (1.0 / 420.0);
-        double pm[10][3], pk[10][3], f[10][3];
+        double pm[10][3], pk[10][3];
 #pragma unroll
         for (int i = 0; i < 10; ++i) {
             const int l = rec.lid[i];
 #pragma unroll
             for (int c = 0; c < 3; ++c) pm[i][c] = lm[3 * l + c];
         }
+        auto emit = [&](int i, double f0, double f1, double f2) {
+            const int l = rec.lid[i];
+            lds_add(la + 3 * l, f0);
+            lds_add(la + 3 * l + 1, f1);
+            lds_add(la + 3 * l + 2, f2);
+            if (MODE == MODE_PCG) pap = fma(pm[i][0], f0, fma(pm[i][1], f1, fma(pm[i][2], f2, pap)));
+        };
         if (MODE == MODE_RHS) {
 #pragma unroll
             for (int i = 0; i < 10; ++i) {
@@ -266,31 +408,33 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
 #pragma unroll
                 for (int c = 0; c < 3; ++c) pk[i][c] = lk[3 * l + c];
             }
-            element_apply(pm, pk, G, lamV, muV, mc, f);
+            element_apply_emit(pm, pk, G, lamV, muV, mc, emit);
         } else {
-            element_apply(pm, pm, G, lamV, muV, mc, f);
-        }
-#pragma unroll
-        for (int i = 0; i < 10; ++i) {
-            const int l = rec.lid[i];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                lds_add(la + 3 * l + c, f[i][c]);
-                if (MODE == MODE_PCG) pap = fma(pm[i][c], f[i][c], pap);
-            }
+            element_apply_emit(pm, pm, G, lamV, muV, mc, emit);
         }
     }
     __syncthreads();
-    for (int j = lane; j < npn; j += 64) {
-        double* q = A.qbuf + 3 * (int64_t)(pn0 + j);
-        q[0] = la[3 * j]; q[1] = la[3 * j + 1]; q[2] = la[3 * j + 2];
+    for (int jb = 0; jb < npn; jb += 64 * GU) {
+        int sl[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int j = jb + lane + 64 * u;
+            sl[u] = j < npn ? P.slot[pn0 + j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int j = jb + lane + 64 * u;
+            if (j >= npn) continue;
+            double* q = A.qbuf + 3 * (int64_t)sl[u];
+            q[0] = la[3 * j]; q[1] = la[3 * j + 1]; q[2] = la[3 * j + 2];
+        }
     }
     __syncthreads();   // LDS is reused by the next patch of a persistent wave
     return pap;
 }
 
 template <int MODE>
-__global__ __launch_bounds__(64) void k_ebe(EbeArgs A) {
+__global__ __launch_bounds__(64, 2) void k_ebe(EbeArgs A) {
     if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
     extern __shared__ double lds[];
     const int patch = xcd_remap(blockIdx.x, gridDim.x);
@@ -332,12 +476,9 @@ __global__ __launch_bounds__(64) void k_ebe_pcg(PcgEbeArgs A) {
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int j = A.j;
-    double zr = 0.0, rr = 0.0, bb = 0.0;
-    for (int i = lane; i < A.g_res; i += 64) {
-        zr += A.res_part[i];
-        rr += A.res_part[A.g_res + i];
-        if (j == 0) bb += A.res_part[2 * A.g_res + i];
-    }
+    double zr = lane_partials<kMaxResGrid / 64>(A.res_part, A.g_res, lane, 64);
+    double rr = lane_partials<kMaxResGrid / 64>(A.res_part + A.g_res, A.g_res, lane, 64);
+    double bb = j == 0 ? lane_partials<kMaxResGrid / 64>(A.res_part + 2 * A.g_res, A.g_res, lane, 64) : 0.0;
     zr = wave_sum(zr);
     rr = wave_sum(rr);
     bb = wave_sum(bb);
@@ -399,8 +540,8 @@ void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool 
 }
 
 int pcg_ebe_grid(const DevPatches& P) {
-    int g = P.n_patches_pad < 2048 ? P.n_patches_pad : 2048;
-    return g;   // n_patches_pad is a multiple of 8, so is g
+    int g = P.n_patches_pad < kMaxPcgGrid ? P.n_patches_pad : kMaxPcgGrid;
+    return g;   // n_patches_pad and kMaxPcgGrid are multiples of 8, so is g
 }
 
 void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const double* p_prev, double* p_cur,
@@ -444,8 +585,8 @@ __global__ __launch_bounds__(64) void k_ebe_diag(DevPatches P, double cm, double
             for (int d = 0; d < 3; ++d) lx[3 * j + d] = P.coords[3 * (int64_t)g + d];
     }
     __syncthreads();
-    if (lane < ne) {
-        const ElemRec rec = P.elems[e0 + lane];
+    for (int e = lane; e < ne; e += 64) {
+        const ElemRec rec = P.elems[e0 + e];
         Geo Gm;
         tet_geo(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], Gm);
         const double* mp = P.mat + 3 * rec.mat;
@@ -481,7 +622,7 @@ __global__ __launch_bounds__(64) void k_ebe_diag(DevPatches P, double cm, double
     }
     __syncthreads();
     for (int j = lane; j < npn; j += 64)
-        for (int t = 0; t < 6; ++t) qbuf6[6 * (int64_t)(pn0 + j) + t] = la[6 * j + t];
+        for (int t = 0; t < 6; ++t) qbuf6[6 * (int64_t)P.slot[pn0 + j] + t] = la[6 * j + t];
 }
 
 void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, double* qbuf6) {
@@ -494,11 +635,11 @@ void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, d
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void gather_q(const DevNodes& N, const double* qbuf, int64_t n, double& q0, double& q1,
                                          double& q2) {
-    q0 = q1 = q2 = 0.0;
-    const int k0 = N.pn_ptr[n], k1 = N.pn_ptr[n + 1];
-    for (int k = k0; k < k1; ++k) {
-        const double* q = qbuf + 3 * (int64_t)N.pn[k];
-        q0 += q[0]; q1 += q[1]; q2 += q[2];
+    const int k0 = N.slot_ptr[n], k1 = N.slot_ptr[n + 1];
+    const double* q = qbuf + 3 * (int64_t)k0;
+    q0 = q[0]; q1 = q[1]; q2 = q[2];
+    for (int k = 1; k < k1 - k0; ++k) {
+        q0 += q[3 * k]; q1 += q[3 * k + 1]; q2 += q[3 * k + 2];
     }
 }
 
@@ -528,8 +669,8 @@ __global__ void k_diag_finalize(DevNodes N, const double* qbuf6, double* binv6) 
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N.n) return;
     double b[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = N.pn_ptr[n]; k < N.pn_ptr[n + 1]; ++k)
-        for (int t = 0; t < 6; ++t) b[t] += qbuf6[6 * (int64_t)N.pn[k] + t];
+    for (int k = N.slot_ptr[n]; k < N.slot_ptr[n + 1]; ++k)
+        for (int t = 0; t < 6; ++t) b[t] += qbuf6[6 * (int64_t)k + t];
     uint8_t fm = N.fixmask[n];
     bool f0 = fm & 1, f1 = fm & 2, f2 = fm & 4;
     double xx = f0 ? 1.0 : b[0], yy = f1 ? 1.0 : b[1], zz = f2 ? 1.0 : b[2];
@@ -595,7 +736,7 @@ void launch_rhs_finalize(hipStream_t s, const DevNodes& N, const double* qbuf, c
 
 int res_grid(int64_t n) {
     int64_t g = (n + 255) / 256;
-    return (int)(g < 512 ? g : 512);
+    return (int)(g < kMaxResGrid ? g : kMaxResGrid);
 }
 
 // r = b - A x (from the slots), z = B^{-1} r; partials of (z,r), (r,r), (b,b)
@@ -658,8 +799,7 @@ void launch_residual(hipStream_t s, const DevNodes& N, const double* qbuf, const
 __global__ __launch_bounds__(256) void k_check_finalize(DevScalars* sc, const double* res_part, int g, int j_next,
                                                         double tol) {
     if (!check_due(sc)) return;
-    double rr = 0.0;
-    for (int i = threadIdx.x; i < g; i += 256) rr += res_part[g + i];
+    double rr = lane_partials<kMaxResGrid / 256>(res_part + g, g, threadIdx.x, 256);
     rr = block_bcast_sum(rr);
     if (threadIdx.x == 0) {
         double res = sqrt(rr) / sc->bnorm;
@@ -688,8 +828,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qb
                                                     DevScalars* sc, const double* pap_part, int g_pap,
                                                     double* res_part, int j) {
     if (sc->done) return;
-    double pap = 0.0;
-    for (int i = threadIdx.x; i < g_pap; i += 256) pap += pap_part[i];
+    double pap = lane_partials<kMaxPcgGrid / 256>(pap_part, g_pap, threadIdx.x, 256);
     pap = block_bcast_sum(pap);
     const double alpha = sc->rho[j & 1] / pap;
     if (!isfinite(alpha)) {
@@ -697,25 +836,46 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qb
         return;
     }
     double v0 = 0.0, v1 = 0.0;
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
-        double q0, q1, q2;
-        gather_q(N, qbuf, n, q0, q1, q2);
-        uint8_t fm = N.fixmask[n];
-        if (fm & 1) q0 = 0.0;
-        if (fm & 2) q1 = 0.0;
-        if (fm & 4) q2 = 0.0;
-        double r0 = fma(-alpha, q0, r[3 * n]);
-        double r1 = fma(-alpha, q1, r[3 * n + 1]);
-        double r2 = fma(-alpha, q2, r[3 * n + 2]);
-        x[3 * n] = fma(alpha, p[3 * n], x[3 * n]);
-        x[3 * n + 1] = fma(alpha, p[3 * n + 1], x[3 * n + 1]);
-        x[3 * n + 2] = fma(alpha, p[3 * n + 2], x[3 * n + 2]);
-        double z0, z1, z2;
-        apply_binv(binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
-        r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
-        z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
-        v0 += z0 * r0 + z1 * r1 + z2 * r2;
-        v1 += r0 * r0 + r1 * r1 + r2 * r2;
+    constexpr int U = 2;   // nodes per thread per trip, loads of all of them issued first
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n0 < N.n; n0 += U * stride) {
+        double q[U][3], rv[U][3], xv[U][3], pv[U][3], B[U][6];
+        uint8_t fm[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t n = n0 + u * stride;
+            const bool ok = n < N.n;
+            if (ok) gather_q(N, qbuf, n, q[u][0], q[u][1], q[u][2]);
+            fm[u] = ok ? N.fixmask[n] : 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                rv[u][c] = ok ? r[3 * n + c] : 0.0;
+                xv[u][c] = ok ? x[3 * n + c] : 0.0;
+                pv[u][c] = ok ? p[3 * n + c] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 6; ++t) B[u][t] = ok ? binv6[6 * n + t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t n = n0 + u * stride;
+            if (n >= N.n) continue;
+            if (fm[u] & 1) q[u][0] = 0.0;
+            if (fm[u] & 2) q[u][1] = 0.0;
+            if (fm[u] & 4) q[u][2] = 0.0;
+            const double r0 = fma(-alpha, q[u][0], rv[u][0]);
+            const double r1 = fma(-alpha, q[u][1], rv[u][1]);
+            const double r2 = fma(-alpha, q[u][2], rv[u][2]);
+            x[3 * n] = fma(alpha, pv[u][0], xv[u][0]);
+            x[3 * n + 1] = fma(alpha, pv[u][1], xv[u][1]);
+            x[3 * n + 2] = fma(alpha, pv[u][2], xv[u][2]);
+            double z0, z1, z2;
+            apply_binv(B[u], r0, r1, r2, z0, z1, z2);
+            r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
+            z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
+            v0 += z0 * r0 + z1 * r1 + z2 * r2;
+            v1 += r0 * r0 + r1 * r1 + r2 * r2;
+        }
     }
     v0 = block_bcast_sum(v0);
     v1 = block_bcast_sum(v1);
@@ -763,33 +923,62 @@ template <int NB>
 __global__ __launch_bounds__(256) void k_gram_solve(ColPtrs W, int s_eff, const int32_t* region_start, double drop,
                                                     double* coef) {
     constexpr int NC = 16 * NB;
+    constexpr int TR = 128;          // rows per LDS tile
+    constexpr int LD = TR + 1;       // odd stride: the 16 columns read by one MFMA operand hit distinct banks
+    constexpr int NT = NB * (NB + 1) / 2;
+    __shared__ double tile[(NC + 1) * LD];
     __shared__ double G[NC][NC + 1];
-    __shared__ double Gw[4][NB * (NB + 1) / 2][4][64];
     __shared__ double hq[4][NC];
     __shared__ double h[NC];
+    double (*Gw)[NT][4][64] = reinterpret_cast<double (*)[NT][4][64]>(tile);   // reuses the tile after the loop
+    static_assert(4 * NT * 4 * 64 <= (NC + 1) * LD, "per-wave tiles must fit in the staging buffer");
     const int r = blockIdx.x;
     const int64_t d0 = 3 * (int64_t)region_start[r], d1 = 3 * (int64_t)region_start[r + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, krow = lane >> 4;
-    const double* A0 = col < s_eff ? W.c[col] : nullptr;
-    const double* A1 = (NB == 2 && 16 + col < s_eff) ? W.c[16 + col] : nullptr;
-    const double* Q = W.c[s_eff];
+    const int ncols = s_eff + 1;     // X columns and the query
+    __shared__ const double* colp[kMaxCols];
+    if (threadIdx.x < ncols) colp[threadIdx.x] = W.c[threadIdx.x];
+    const bool use0 = col < s_eff, use1 = NB == 2 && 16 + col < s_eff;
     double4_t c00 = {0, 0, 0, 0}, c01 = {0, 0, 0, 0}, c11 = {0, 0, 0, 0};
     double h0 = 0.0, h1 = 0.0;
-    for (int64_t base = d0 + 4 * wave; base < d1; base += 16) {
-        int64_t row = base + krow;
-        bool ok = row < d1;
-        double a0 = (ok && A0) ? A0[row] : 0.0;
-        double a1 = (NB == 2 && ok && A1) ? A1[row] : 0.0;
-        double q = ok ? Q[row] : 0.0;
-        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, c00, 0, 0, 0);
-        if (NB == 2) {
-            c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, c01, 0, 0, 0);
-            c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, c11, 0, 0, 0);
-        }
-        h0 = fma(a0, q, h0);
-        h1 = fma(a1, q, h1);
+    // staging map: thread t copies row t % TR of columns t / TR, t / TR + 2, ...
+    constexpr int CPT = (NC + 2) / 2;          // columns per thread (ceil((NC + 1) / 2))
+    const int srow = threadIdx.x % TR, sc0 = threadIdx.x / TR;
+    __syncthreads();
+    const double* sp[CPT];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+        const int c = sc0 + 2 * k;
+        sp[k] = c < ncols ? colp[c] : nullptr;
     }
+    for (int64_t base = d0; base < d1; base += TR) {
+        const int64_t row = base + srow;
+        double v[CPT];
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) v[k] = (sp[k] && row < d1) ? sp[k][row] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+            if (sp[k]) tile[(sc0 + 2 * k) * LD + srow] = v[k];
+        __syncthreads();
+        // each wave owns 32 rows of the tile: 8 k-steps of 4 rows
+#pragma unroll
+        for (int t = 0; t < TR / 16; ++t) {
+            const int rr = wave * (TR / 4) + 4 * t + krow;
+            const double a0 = use0 ? tile[col * LD + rr] : 0.0;
+            const double a1 = use1 ? tile[(16 + col) * LD + rr] : 0.0;
+            const double q = tile[s_eff * LD + rr];
+            c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a0, c00, 0, 0, 0);
+            if (NB == 2) {
+                c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, a1, c01, 0, 0, 0);
+                c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, a1, c11, 0, 0, 0);
+            }
+            h0 = fma(a0, q, h0);
+            h1 = fma(a1, q, h1);
+        }
+    }
+    __syncthreads();   // the staging buffer becomes Gw
     // per-wave tiles to LDS: register v of lane l holds D[l/16 + 4 v][l%16]
     for (int v = 0; v < 4; ++v) {
         Gw[wave][0][v][lane] = c00[v];
@@ -853,8 +1042,8 @@ __global__ __launch_bounds__(256) void k_gram_solve(ColPtrs W, int s_eff, const 
         __syncthreads();
     }
     // forward solve R^T y = h_scaled (sequential, lane 0), back solve R a = y
+    __shared__ double y[NC];
     if (w0 && lane == 0) {
-        double y[NC];
         for (int j = 0; j < s; ++j) {
             double t = h[j] / (dsc[j] > 0 ? dsc[j] : 1.0);
             for (int i = 0; i < j; ++i) t -= G[i][j] * y[i];
@@ -885,6 +1074,7 @@ __global__ __launch_bounds__(256) void k_pred_apply(ColPtrs W, int s_eff, const 
     const double* a = coef + 32 * (int64_t)r;
     for (int64_t i = d0 + threadIdx.x; i < d1; i += 256) {
         double t = dab[i];
+#pragma unroll 8
         for (int j = 0; j < s_eff; ++j) t = fma(a[j], W.c[j + 1][i], t);
         x[i] = t;
     }

@@ -6,10 +6,11 @@
 // Element order: by the lowest internal id among the element's vertices,
 // ties broken by the Morton code of the centroid.  Consecutive runs of
 // patch_elems elements form a patch; a patch is processed by one 64-wide
-// wavefront that stages the patch's nodes in LDS.  Each patch lists its nodes
-// (vertices first, so the geometry gather touches a prefix only) and every
-// node lists the patch slots it receives contributions from, in patch order,
-// which fixes the summation order and makes results bitwise reproducible.
+// wavefront (up to two elements per lane) that stages the patch's nodes in LDS.  Each patch lists its nodes
+// (vertices first, so the geometry gather touches a prefix only).  Each
+// (patch, node) pair writes its partial result to its own slot; the slots of a
+// node are contiguous and in patch order, which fixes the summation order and
+// makes results bitwise reproducible.
 #include "topology.h"
 
 #include <algorithm>
@@ -60,7 +61,7 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     if (N <= 0 || E <= 0) return "mesh must have nodes and elements";
     if (N >= (int64_t)1 << 31 || E >= (int64_t)1 << 31) return "mesh too large for 32-bit ids";
     if (n_mat <= 0 || n_mat > 65535) return "n_mat must be in [1, 65535]";
-    if (patch_elems <= 0 || patch_elems > kMaxPatchElems) return "patch_elems must be in [1, 64]";
+    if (patch_elems <= 0 || patch_elems > kMaxPatchElems) return "patch_elems must be in [1, 128]";
     T = Topology();
     T.n_nodes = N;
     T.n_elems = E;
@@ -238,15 +239,15 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     }
     if ((int64_t)T.patch_nodes.size() >= ((int64_t)1 << 31)) return "too many patch nodes";
 
-    // ---- per-node slot lists (patch order)
-    T.node_pn_ptr.assign(N + 1, 0);
-    for (uint32_t ent : T.patch_nodes) T.node_pn_ptr[(ent & ~kOwnerBit) + 1]++;
-    for (int64_t v = 0; v < N; ++v) T.node_pn_ptr[v + 1] += T.node_pn_ptr[v];
-    T.node_pn.resize(T.patch_nodes.size());
-    std::vector<int32_t> pos(T.node_pn_ptr.begin(), T.node_pn_ptr.end() - 1);
-    for (size_t k = 0; k < T.patch_nodes.size(); ++k) T.node_pn[pos[T.patch_nodes[k] & ~kOwnerBit]++] = (int32_t)k;
+    // ---- node-major slots (patch order within a node)
+    T.slot_ptr.assign(N + 1, 0);
+    for (uint32_t ent : T.patch_nodes) T.slot_ptr[(ent & ~kOwnerBit) + 1]++;
+    for (int64_t v = 0; v < N; ++v) T.slot_ptr[v + 1] += T.slot_ptr[v];
+    T.patch_slot.resize(T.patch_nodes.size());
+    std::vector<int32_t> pos(T.slot_ptr.begin(), T.slot_ptr.end() - 1);
+    for (size_t k = 0; k < T.patch_nodes.size(); ++k) T.patch_slot[k] = pos[T.patch_nodes[k] & ~kOwnerBit]++;
     for (int64_t v = 0; v < N; ++v)
-        if (T.node_pn_ptr[v + 1] == T.node_pn_ptr[v]) return "internal error: node without patch";
+        if (T.slot_ptr[v + 1] == T.slot_ptr[v]) return "internal error: node without patch";
     return std::string();
 }
 

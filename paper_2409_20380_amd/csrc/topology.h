@@ -11,7 +11,7 @@ namespace ebe {
 // Bit set on a patch-node entry when that patch is the first (owner) patch of
 // the node: the owner writes per-node values that every touching patch computes.
 constexpr uint32_t kOwnerBit = 0x80000000u;
-constexpr int kMaxPatchElems = 64;   // one element per lane of a 64-wide wavefront
+constexpr int kMaxPatchElems = 128;  // at most two elements per lane of a 64-wide wavefront
 
 // Element record used by the kernels: ten patch-local node indices (vertices
 // first, then edges in the conn order), the material id and one pad word.
@@ -39,9 +39,12 @@ struct Topology {
     std::vector<uint32_t> patch_nodes;      // [PN] internal node id | kOwnerBit
     std::vector<ElemRec> elems;             // [E] internal element order
     int32_t max_pn = 0, max_nv = 0;
-    // per node: patch-node slots it receives contributions from (in patch order)
-    std::vector<int32_t> node_pn_ptr;       // [N+1]
-    std::vector<int32_t> node_pn;           // [PN]
+    // Slots: every (patch, node) pair owns one 3-vector of the matvec output.
+    // Slots are numbered node-major: node n owns [slot_ptr[n], slot_ptr[n+1]),
+    // one per touching patch in patch order; patch_slot[pn] is the slot that
+    // patch-node pn writes.
+    std::vector<int32_t> slot_ptr;          // [N+1]
+    std::vector<int32_t> patch_slot;        // [PN]
     // material table: lambda, mu, rho
     std::vector<double> mat_lmr;
 };

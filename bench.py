@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.json"))
-    ap.add_argument("--patch-elems", type=int, default=128, help="elements per EBE patch (1..128)")
+    ap.add_argument("--patch-elems", type=int, default=256, help="elements per EBE patch (1..256)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB device-to-device once (counter calibration)")
     args = ap.parse_args()

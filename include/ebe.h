@@ -77,7 +77,7 @@ typedef struct {
     int32_t predictor;      /* EBE_PRED_* */
     int32_t region_nodes;   /* nodes per predictor region when ebe_assemble receives no
                                region map (<= 0: 512) */
-    int32_t patch_elems;    /* elements per EBE patch, 1..128 (<= 0: 128) */
+    int32_t patch_elems;    /* elements per EBE patch, 1..256 (<= 0: 256) */
     int32_t chunk_iters;    /* PCG iterations enqueued between convergence checks
                                (<= 0: adaptive) */
     int32_t reserved[6];

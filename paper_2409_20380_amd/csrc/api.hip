@@ -67,7 +67,7 @@ struct ebe_handle {
     int32_t it = 0;
     // scratch
     double *dab = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr};
-    double *t0 = nullptr, *t1 = nullptr, *coef = nullptr;
+    double *t0 = nullptr, *t1 = nullptr, *coef = nullptr, *gh = nullptr;
     int par = 0;
     int last_iters = 0;
     DevScalars* sc = nullptr;
@@ -299,7 +299,7 @@ int predict_into(ebe_handle* h, double* x) {
             int m = n - s_eff - 1 + j;  // e^m, stored in slot (m - 1) mod (s + 1)
             W.c[j] = h->ring_slot((m - 1) % S1);
         }
-        launch_gram_solve(s, W, s_eff, h->T.n_regions, h->d_region_start, h->cfg.drop_tol, h->coef);
+        launch_gram_solve(s, W, s_eff, h->T.n_regions, h->d_region_start, h->cfg.drop_tol, h->gh, h->coef);
         launch_pred_apply(s, W, s_eff, h->T.n_regions, h->d_region_start, h->coef, h->dab, x);
     }
     check_launch();
@@ -334,7 +334,7 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     if (!(c.dt > 0) || !(c.tol > 0) || c.s < 0 || c.s > 32 || c.predictor < 0 || c.predictor > 2 ||
         c.rayleigh_alpha < 0 || c.rayleigh_beta < 0 || c.patch_elems > kMaxPatchElems) {
         g_create_error = "invalid configuration (need dt > 0, tol > 0, 0 <= s <= 32, predictor in 0..2, "
-                         "non-negative damping, patch_elems <= 128)";
+                         "non-negative damping, patch_elems <= 256)";
         return EBE_E_INVALID_ARG;
     }
     if (c.max_iter <= 0) c.max_iter = 10000;
@@ -399,6 +399,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->dp.max_pn = T.max_pn;
         h->dp.max_nv = T.max_nv;
         h->dn.slot_ptr = h->upload(T.slot_ptr);
+        if (!ebe_set_lds_limit(h->dp)) throw Arg{"an element patch needs more LDS than the device allows; lower patch_elems"};
         h->dn.fixmask = fm;
         h->dn.n = N;
         h->d_i2u = h->upload(T.i2u);
@@ -422,6 +423,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->t0 = h->alloc<double>(n3);
         h->t1 = h->alloc<double>(n3);
         h->coef = h->alloc<double>(32 * (size_t)T.n_regions);
+        h->gh = h->alloc<double>((size_t)kGhStride * T.n_regions);
         h->sc = h->alloc<DevScalars>(1);
         h->pap_part = h->alloc<double>(pcg_ebe_grid(h->dp));
         h->res_part = h->alloc<double>(2 * 3 * (size_t)res_grid(N));

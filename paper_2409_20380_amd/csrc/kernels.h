@@ -48,7 +48,8 @@ struct DevNodes {
 };
 
 constexpr int kMaxCols = 33;    // s <= 32 input columns plus the query
-constexpr int kMaxPcgGrid = 2048;   // persistent workgroups of the PCG matvec (multiple of 8)
+constexpr int kEbeWaves = 4;        // wavefronts per EBE workgroup (one patch per workgroup)
+constexpr int kMaxPcgGrid = 512;    // persistent workgroups of the PCG matvec (multiple of 8)
 constexpr int kMaxResGrid = 1024;   // workgroups of the node-wise reduction kernels
 struct ColPtrs {
     const double* c[kMaxCols];
@@ -71,6 +72,10 @@ void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const d
                     double c1, double c2, double g0, double g1, double g2, double* qbuf);
 // Block diagonal of cm M + ck K per patch node (6 symmetric entries).
 void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, double* qbuf6);
+// Dynamic LDS of the element kernels for this topology, and the opt-in that
+// lets them use more than the default 64 KiB (returns false if refused).
+size_t ebe_lds_bytes(const DevPatches& P, int mode);
+bool ebe_set_lds_limit(const DevPatches& P);
 
 // ---- node-wise kernels
 void launch_combine_apply(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, int mode, double* q);
@@ -91,8 +96,9 @@ void launch_pcg_update(hipStream_t s, const DevNodes& N, const double* qbuf, con
 // ---- predictor and time integration (all lengths in dofs, 3N)
 void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const double* v2, const double* v3,
                 const double* v4, int kind, double* dab, double* x);
+constexpr int kGhStride = 32 * 32 + 32;   // per-region Gram [32][32] followed by X^T q [32]
 void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
-                       double drop, double* coef);
+                       double drop, double* gh, double* coef);
 void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
                        const double* coef, const double* dab, double* x);
 void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, const double* dab, double* u,

@@ -292,34 +292,39 @@ __device__ __forceinline__ bool check_due(const DevScalars* sc) {
     return (sc->done == DONE_CONVERGED || sc->done == DONE_MAXITER) && !sc->checked;
 }
 
-// One patch on one wavefront.  Returns this lane's share of (p, A p) (PCG).
+// One patch on one workgroup of kEbeWaves wavefronts (one element per lane).
+// The waves share the gather of the patch's nodes into LDS; wave w adds its
+// elements' results into its own LDS accumulator (a single wave issues its
+// LDS atomics in program order), and the kEbeWaves accumulators are summed in
+// a fixed order: results are bitwise reproducible.  Returns this thread's
+// share of (p, A p) (PCG).
 template <int MODE>
 __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double beta, double* lds) {
     const DevPatches& P = A.P;
-    const int lane = threadIdx.x & 63;
+    constexpr int NT = 64 * kEbeWaves;
+    const int tid = threadIdx.x, wave = tid >> 6;
     const int pn0 = P.pn_ptr[patch], npn = P.pn_ptr[patch + 1] - pn0;
     const int nv = P.nv[patch];
     const int e0 = P.el_ptr[patch], ne = P.el_ptr[patch + 1] - e0;
-    double* lm = lds;                          // [max_pn][3] mass operand (or shared operand)
-    double* lk = lm + 3 * P.max_pn;            // [max_pn][3] stiffness operand (RHS only)
-    double* la = lk + (MODE == MODE_RHS ? 3 * P.max_pn : 0);   // [max_pn][3] accumulator
-    double* lx = la + 3 * P.max_pn;            // [max_nv][3] vertex coordinates
+    const int stride = 3 * P.max_pn;
+    double* lm = lds;                                           // [max_pn][3] mass (or shared) operand
+    double* lk = lm + stride;                                   // [max_pn][3] stiffness operand (RHS)
+    double* la = lk + (MODE == MODE_RHS ? stride : 0);          // kEbeWaves x [max_pn][3] accumulators
+    double* lx = la + kEbeWaves * stride;                       // [max_nv][3] vertex coordinates
 
-    // Gather: the patch's node list is walked in groups of GU x 64 entries; all
-    // loads of a group are issued before any is consumed (memory-level
-    // parallelism instead of one dependent round trip per 64 nodes).
-    constexpr int GU = 4;
-    for (int jb = 0; jb < npn; jb += 64 * GU) {
+    // Gather: all loads of a group of GU x NT node entries are issued before any is consumed.
+    constexpr int GU = 2;
+    for (int jb = 0; jb < npn; jb += NT * GU) {
         uint32_t ent[GU];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
-            const int j = jb + lane + 64 * u;
+            const int j = jb + tid + NT * u;
             ent[u] = j < npn ? P.nodes[pn0 + j] : 0u;
         }
         double v[GU][3], w[GU][3], xc[GU][3];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
-            const int j = jb + lane + 64 * u;
+            const int j = jb + tid + NT * u;
             const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
             const bool ok = j < npn;
 #pragma unroll
@@ -333,7 +338,7 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
         if (MODE == MODE_RHS) {
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
-                const int j = jb + lane + 64 * u;
+                const int j = jb + tid + NT * u;
                 const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) a3[u][c] = j < npn ? A.in2[3 * g + c] : 0.0;
@@ -341,7 +346,7 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
         }
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
-            const int j = jb + lane + 64 * u;
+            const int j = jb + tid + NT * u;
             if (j >= npn) continue;
             const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
             double v0 = v[u][0], v1 = v[u][1], v2 = v[u][2];
@@ -369,7 +374,10 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
                 lk[3 * j + 2] = fma(A.c2, w[u][2], -u2);
             }
             lm[3 * j] = v0; lm[3 * j + 1] = v1; lm[3 * j + 2] = v2;
-            la[3 * j] = 0.0; la[3 * j + 1] = 0.0; la[3 * j + 2] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kEbeWaves; ++q) {
+                la[q * stride + 3 * j] = 0.0; la[q * stride + 3 * j + 1] = 0.0; la[q * stride + 3 * j + 2] = 0.0;
+            }
             if (j < nv) {
                 lx[3 * j] = xc[u][0]; lx[3 * j + 1] = xc[u][1]; lx[3 * j + 2] = xc[u][2];
             }
@@ -378,9 +386,9 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     __syncthreads();
 
     double pap = 0.0;
-#pragma unroll 1
-    for (int e = lane; e < ne; e += 64) {   // up to two elements per lane, in program order
-        const ElemRec rec = P.elems[e0 + e];
+    if (tid < ne) {
+        double* acc = la + wave * stride;
+        const ElemRec rec = P.elems[e0 + tid];
         Geo G;
         tet_geo(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
         const double* mp = P.mat + 3 * rec.mat;
@@ -396,9 +404,9 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
         }
         auto emit = [&](int i, double f0, double f1, double f2) {
             const int l = rec.lid[i];
-            lds_add(la + 3 * l, f0);
-            lds_add(la + 3 * l + 1, f1);
-            lds_add(la + 3 * l + 2, f2);
+            lds_add(acc + 3 * l, f0);
+            lds_add(acc + 3 * l + 1, f1);
+            lds_add(acc + 3 * l + 2, f2);
             if (MODE == MODE_PCG) pap = fma(pm[i][0], f0, fma(pm[i][1], f1, fma(pm[i][2], f2, pap)));
         };
         if (MODE == MODE_RHS) {
@@ -414,35 +422,42 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
         }
     }
     __syncthreads();
-    for (int jb = 0; jb < npn; jb += 64 * GU) {
+    for (int jb = 0; jb < npn; jb += NT * GU) {
         int sl[GU];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
-            const int j = jb + lane + 64 * u;
+            const int j = jb + tid + NT * u;
             sl[u] = j < npn ? P.slot[pn0 + j] : 0;
         }
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
-            const int j = jb + lane + 64 * u;
+            const int j = jb + tid + NT * u;
             if (j >= npn) continue;
-            double* q = A.qbuf + 3 * (int64_t)sl[u];
-            q[0] = la[3 * j]; q[1] = la[3 * j + 1]; q[2] = la[3 * j + 2];
+            double q0 = la[3 * j], q1 = la[3 * j + 1], q2 = la[3 * j + 2];
+#pragma unroll
+            for (int q = 1; q < kEbeWaves; ++q) {
+                q0 += la[q * stride + 3 * j];
+                q1 += la[q * stride + 3 * j + 1];
+                q2 += la[q * stride + 3 * j + 2];
+            }
+            double* qo = A.qbuf + 3 * (int64_t)sl[u];
+            qo[0] = q0; qo[1] = q1; qo[2] = q2;
         }
     }
-    __syncthreads();   // LDS is reused by the next patch of a persistent wave
+    __syncthreads();   // LDS is reused by the next patch of a persistent workgroup
     return pap;
 }
 
 template <int MODE>
-__global__ __launch_bounds__(64, 2) void k_ebe(EbeArgs A) {
+__global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
     if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
     extern __shared__ double lds[];
     const int patch = xcd_remap(blockIdx.x, gridDim.x);
     ebe_patch<MODE>(A, patch, 0.0, lds);
 }
 
-static size_t ebe_lds_bytes(const DevPatches& P, int mode) {
-    return sizeof(double) * (size_t)(3 * P.max_pn * (mode == MODE_RHS ? 3 : 2) + 3 * P.max_nv);
+size_t ebe_lds_bytes(const DevPatches& P, int mode) {
+    return sizeof(double) * (size_t)(3 * P.max_pn * ((mode == MODE_RHS ? 2 : 1) + kEbeWaves) + 3 * P.max_nv);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,18 +485,21 @@ struct PcgEbeArgs {
 // beta = rho_j / rho_{j-1} (0 on the first trip of a cycle), p = z + beta p,
 // q = A p (patch slots) and the partials of (p, A p).  Persistent grid: each
 // workgroup walks a contiguous (per XCD) range of patches.
-__global__ __launch_bounds__(64) void k_ebe_pcg(PcgEbeArgs A) {
+__device__ __forceinline__ double block_bcast_sum(double v);
+
+__global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe_pcg(PcgEbeArgs A) {
     DevScalars* sc = A.sc;
     if (sc->done) return;
     extern __shared__ double lds[];
-    const int lane = threadIdx.x;
+    constexpr int NT = 64 * kEbeWaves;
+    const int tid = threadIdx.x;
     const int j = A.j;
-    double zr = lane_partials<kMaxResGrid / 64>(A.res_part, A.g_res, lane, 64);
-    double rr = lane_partials<kMaxResGrid / 64>(A.res_part + A.g_res, A.g_res, lane, 64);
-    double bb = j == 0 ? lane_partials<kMaxResGrid / 64>(A.res_part + 2 * A.g_res, A.g_res, lane, 64) : 0.0;
-    zr = wave_sum(zr);
-    rr = wave_sum(rr);
-    bb = wave_sum(bb);
+    double zr = lane_partials<kMaxResGrid / NT>(A.res_part, A.g_res, tid, NT);
+    double rr = lane_partials<kMaxResGrid / NT>(A.res_part + A.g_res, A.g_res, tid, NT);
+    double bb = j == 0 ? lane_partials<kMaxResGrid / NT>(A.res_part + 2 * A.g_res, A.g_res, tid, NT) : 0.0;
+    zr = block_bcast_sum(zr);
+    rr = block_bcast_sum(rr);
+    bb = block_bcast_sum(bb);
     const double bnorm = (j == 0) ? sqrt(bb) : sc->bnorm;
     const double res = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
     int stop = DONE_RUNNING;
@@ -494,7 +512,7 @@ __global__ __launch_bounds__(64) void k_ebe_pcg(PcgEbeArgs A) {
         beta = zr / sc->rho[(j - 1) & 1];
         if (!isfinite(beta)) stop = DONE_NONFINITE;
     }
-    if (blockIdx.x == 0 && lane == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         if (j == 0) {
             sc->bnorm = bnorm;
             sc->res0 = res;
@@ -515,8 +533,8 @@ __global__ __launch_bounds__(64) void k_ebe_pcg(PcgEbeArgs A) {
     const int chunk = A.E.P.n_patches_pad >> 3;
     double pap = 0.0;
     for (int k = k0; k < chunk; k += per_xcd_wg) pap += ebe_patch<MODE_PCG>(A.E, xcd * chunk + k, beta, lds);
-    pap = wave_sum(pap);
-    if (lane == 0) A.pap_part[blockIdx.x] = pap;
+    pap = block_bcast_sum(pap);
+    if (tid == 0) A.pap_part[blockIdx.x] = pap;
 }
 
 __device__ __forceinline__ double block_bcast_sum(double v) {
@@ -531,12 +549,29 @@ __device__ __forceinline__ double block_bcast_sum(double v) {
     return out;
 }
 
+bool ebe_set_lds_limit(const DevPatches& P) {
+    const size_t need = ebe_lds_bytes(P, MODE_RHS);
+    if (need <= 65536) return true;
+    int dev = 0, maxlds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
+    if (need > (size_t)maxlds) return false;
+    const int v = (int)need;
+    bool ok = hipFuncSetAttribute((const void*)k_ebe<MODE_APPLY>, hipFuncAttributeMaxDynamicSharedMemorySize, v) ==
+              hipSuccess;
+    ok = ok && hipFuncSetAttribute((const void*)k_ebe<MODE_RHS>, hipFuncAttributeMaxDynamicSharedMemorySize, v) ==
+                   hipSuccess;
+    ok = ok && hipFuncSetAttribute((const void*)k_ebe_pcg, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess;
+    return ok;
+}
+
 void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
                       double* qbuf, const DevScalars* guard) {
     EbeArgs A{};
     A.P = P; A.in0 = p; A.qbuf = qbuf; A.cm = cm; A.ck = ck; A.mask_in = mask_in ? 1 : 0;
     A.guard = guard;
-    hipLaunchKernelGGL(k_ebe<MODE_APPLY>, dim3(P.n_patches_pad), dim3(64), ebe_lds_bytes(P, MODE_APPLY), s, A);
+    hipLaunchKernelGGL(k_ebe<MODE_APPLY>, dim3(P.n_patches_pad), dim3(64 * kEbeWaves), ebe_lds_bytes(P, MODE_APPLY), s,
+                       A);
 }
 
 int pcg_ebe_grid(const DevPatches& P) {
@@ -551,7 +586,7 @@ void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const d
     A.E.P = P; A.E.in0 = z; A.E.in1 = p_prev; A.E.p_cur = p_cur; A.E.qbuf = qbuf; A.E.cm = cm; A.E.ck = ck;
     A.sc = sc; A.res_part = res_part; A.g_res = g_res; A.pap_part = pap_part; A.j = j; A.max_iter = max_iter;
     A.tol = tol;
-    hipLaunchKernelGGL(k_ebe_pcg, dim3(pcg_ebe_grid(P)), dim3(64), ebe_lds_bytes(P, MODE_PCG), s, A);
+    hipLaunchKernelGGL(k_ebe_pcg, dim3(pcg_ebe_grid(P)), dim3(64 * kEbeWaves), ebe_lds_bytes(P, MODE_PCG), s, A);
 }
 
 void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const double* v, const double* a,
@@ -559,7 +594,7 @@ void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const d
     EbeArgs A{};
     A.P = P; A.in0 = u; A.in1 = v; A.in2 = a; A.qbuf = qbuf; A.cm = 1.0; A.ck = 1.0;
     A.c1 = c1; A.c2 = c2; A.g0 = g0; A.g1 = g1; A.g2 = g2;
-    hipLaunchKernelGGL(k_ebe<MODE_RHS>, dim3(P.n_patches_pad), dim3(64), ebe_lds_bytes(P, MODE_RHS), s, A);
+    hipLaunchKernelGGL(k_ebe<MODE_RHS>, dim3(P.n_patches_pad), dim3(64 * kEbeWaves), ebe_lds_bytes(P, MODE_RHS), s, A);
 }
 
 // ---------------------------------------------------------------------------
@@ -913,23 +948,17 @@ void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const do
     hipLaunchKernelGGL(k_ab4, dim3(nb), dim3(256), 0, s, n3, dt, v1, v2, v3, v4, kind, dab, x);
 }
 
-// Regional Gram products on FP64 MFMA (v_mfma_f64_16x16x4f64) followed by the
-// least-squares solve.  W = [x_1 .. x_s, q]: X^T X comes from 16x16 tiles,
-// X^T q from per-lane FMAs.  The s x s system is solved by a Cholesky
-// factorisation taken column by column in time order; a column whose
-// remaining (orthogonal) part falls below drop * its norm is dropped, which
-// reproduces the column selection of modified Gram-Schmidt in that order.
+// Regional Gram products on FP64 MFMA (v_mfma_f64_16x16x4f64).  For the
+// region's rows of W = [x_1 .. x_s, q]: X^T X from 16x16 tiles and X^T q from
+// per-lane FMAs, written to gh[r] = [32][32] Gram followed by [32] X^T q.
 template <int NB>
-__global__ __launch_bounds__(256) void k_gram_solve(ColPtrs W, int s_eff, const int32_t* region_start, double drop,
-                                                    double* coef) {
+__global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_t* region_start, double* gh) {
     constexpr int NC = 16 * NB;
     constexpr int TR = 128;          // rows per LDS tile
     constexpr int LD = TR + 1;       // odd stride: the 16 columns read by one MFMA operand hit distinct banks
     constexpr int NT = NB * (NB + 1) / 2;
     __shared__ double tile[(NC + 1) * LD];
-    __shared__ double G[NC][NC + 1];
     __shared__ double hq[4][NC];
-    __shared__ double h[NC];
     double (*Gw)[NT][4][64] = reinterpret_cast<double (*)[NT][4][64]>(tile);   // reuses the tile after the loop
     static_assert(4 * NT * 4 * 64 <= (NC + 1) * LD, "per-wave tiles must fit in the staging buffer");
     const int r = blockIdx.x;
@@ -996,74 +1025,91 @@ __global__ __launch_bounds__(256) void k_gram_solve(ColPtrs W, int s_eff, const 
         if (NB == 2) hq[wave][16 + lane] = h1;
     }
     __syncthreads();
-    // sum over waves (fixed order) and assemble the symmetric Gram
-    for (int idx = threadIdx.x; idx < 4 * 64 * (NB * (NB + 1) / 2); idx += 256) {
+    // sum over waves (fixed order) and store the symmetric Gram
+    double* out = gh + (int64_t)r * kGhStride;
+    for (int idx = threadIdx.x; idx < 4 * 64 * NT; idx += 256) {
         int t = idx / 256, rem = idx % 256, v = rem / 64, l = rem % 64;
-        double s = (Gw[0][t][v][l] + Gw[1][t][v][l]) + (Gw[2][t][v][l] + Gw[3][t][v][l]);
+        double sum = (Gw[0][t][v][l] + Gw[1][t][v][l]) + (Gw[2][t][v][l] + Gw[3][t][v][l]);
         int i = (l / 16) + 4 * v, j = l % 16;
         int bi = (t == 2) ? 1 : 0, bj = (t == 0) ? 0 : 1;
-        G[16 * bi + i][16 * bj + j] = s;
-        if (bi != bj) G[16 * bj + j][16 * bi + i] = s;
+        out[(16 * bi + i) * 32 + 16 * bj + j] = sum;
+        if (bi != bj) out[(16 * bj + j) * 32 + 16 * bi + i] = sum;
     }
-    if (threadIdx.x < NC) h[threadIdx.x] = (hq[0][threadIdx.x] + hq[1][threadIdx.x]) + (hq[2][threadIdx.x] + hq[3][threadIdx.x]);
+    if (threadIdx.x < NC)
+        out[1024 + threadIdx.x] = (hq[0][threadIdx.x] + hq[1][threadIdx.x]) + (hq[2][threadIdx.x] + hq[3][threadIdx.x]);
+}
+
+// Least-squares coefficients of one region (one 64-lane workgroup): with
+// column scaling d_j = sqrt(G_jj), Cholesky of the scaled Gram taken column by
+// column in time order; a column whose remaining (orthogonal) part is below
+// drop * its norm is dropped, which reproduces the column selection of
+// modified Gram-Schmidt in that order.  Then R^T y = h, R a = y, coef = a / d.
+__global__ __launch_bounds__(64) void k_ls_solve(const double* gh, int s, double drop, double* coef) {
+    __shared__ double G[32][33];
+    __shared__ double y[32], d[32];
+    __shared__ int keep[32];
+    const int r = blockIdx.x, lane = threadIdx.x;
+    const double* in = gh + (int64_t)r * kGhStride;
+    for (int idx = lane; idx < s * s; idx += 64) {
+        const int i = idx / s, j = idx - i * s;
+        G[i][j] = in[i * 32 + j];
+    }
+    if (lane < s) y[lane] = in[1024 + lane];
     __syncthreads();
-    // Column scaling, Cholesky with the time-ordered drop rule and the two
-    // triangular solves run on wave 0; the other waves only join the barriers.
-    const bool w0 = (wave == 0);
-    const int s = s_eff;
-    __shared__ double dsc[NC];
-    __shared__ int keep[NC];
-    double d = (w0 && lane < s) ? sqrt(G[lane][lane]) : 0.0;
-    if (w0 && lane < NC) dsc[lane] = d;
+    if (lane < s) {
+        d[lane] = sqrt(G[lane][lane]);
+        keep[lane] = 0;
+    }
     __syncthreads();
-    if (w0 && lane < s)
-        for (int i = 0; i < s; ++i) {
-            double di = dsc[i];
-            G[i][lane] = (di > 0 && d > 0) ? G[i][lane] / (di * d) : 0.0;
-        }
-    if (w0 && lane < NC) keep[lane] = 0;
+    for (int idx = lane; idx < s * s; idx += 64) {
+        const int i = idx / s, j = idx - i * s;
+        G[i][j] = (d[i] > 0.0 && d[j] > 0.0) ? G[i][j] / (d[i] * d[j]) : 0.0;
+    }
+    if (lane < s) y[lane] = d[lane] > 0.0 ? y[lane] / d[lane] : 0.0;
     __syncthreads();
     const double drop2 = drop * drop;
     for (int j = 0; j < s; ++j) {
-        double t = G[j][j];
-        bool kj = (dsc[j] > 0) && (t >= drop2);
-        double rjj = kj ? sqrt(t) : 0.0;
+        const double t = G[j][j];
+        const bool kj = d[j] > 0.0 && t >= drop2;
+        const double rjj = kj ? sqrt(t) : 0.0;
         __syncthreads();
-        // row j of R: R[j][k] = G[j][k] / rjj for k > j
-        if (w0 && lane > j && lane < s) G[j][lane] = kj ? G[j][lane] / rjj : 0.0;
-        if (w0 && lane == 0) {
+        if (lane > j && lane < s) G[j][lane] = kj ? G[j][lane] / rjj : 0.0;
+        if (lane == 0) {
             G[j][j] = rjj;
             keep[j] = kj;
         }
         __syncthreads();
-        // trailing update: G[k][l] -= R[j][k] R[j][l], k, l > j (lanes over l)
-        if (w0 && kj && lane > j && lane < s)
-            for (int k = j + 1; k < s; ++k) G[k][lane] -= G[j][k] * G[j][lane];
+        if (kj) {  // trailing update of the upper triangle, entries spread over the lanes
+            const int m = s - j - 1;
+            for (int idx = lane; idx < m * m; idx += 64) {
+                const int k = j + 1 + idx / m, l = j + 1 + idx % m;
+                if (l >= k) G[k][l] -= G[j][k] * G[j][l];
+            }
+        }
         __syncthreads();
     }
-    // forward solve R^T y = h_scaled (sequential, lane 0), back solve R a = y
-    __shared__ double y[NC];
-    if (w0 && lane == 0) {
-        for (int j = 0; j < s; ++j) {
-            double t = h[j] / (dsc[j] > 0 ? dsc[j] : 1.0);
-            for (int i = 0; i < j; ++i) t -= G[i][j] * y[i];
-            y[j] = keep[j] ? t / G[j][j] : 0.0;
-        }
-        for (int j = s - 1; j >= 0; --j) {
-            double t = y[j];
-            for (int k = j + 1; k < s; ++k) t -= G[j][k] * y[k];
-            y[j] = keep[j] ? t / G[j][j] : 0.0;
-        }
-        for (int j = 0; j < 32; ++j) coef[32 * (int64_t)r + j] = (j < s && keep[j]) ? y[j] / dsc[j] : 0.0;
+    for (int j = 0; j < s; ++j) {      // R^T y = h (column-oriented)
+        if (lane == j) y[j] = keep[j] ? y[j] / G[j][j] : 0.0;
+        __syncthreads();
+        if (lane > j && lane < s) y[lane] -= G[j][lane] * y[j];
+        __syncthreads();
     }
+    for (int j = s - 1; j >= 0; --j) { // R a = y
+        if (lane == j) y[j] = keep[j] ? y[j] / G[j][j] : 0.0;
+        __syncthreads();
+        if (lane < j) y[lane] -= G[lane][j] * y[j];
+        __syncthreads();
+    }
+    if (lane < 32) coef[32 * (int64_t)r + lane] = (lane < s && keep[lane]) ? y[lane] / d[lane] : 0.0;
 }
 
 void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
-                       double drop, double* coef) {
+                       double drop, double* gh, double* coef) {
     if (s_eff <= 16)
-        hipLaunchKernelGGL(k_gram_solve<1>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, drop, coef);
+        hipLaunchKernelGGL(k_gram<1>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, gh);
     else
-        hipLaunchKernelGGL(k_gram_solve<2>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, drop, coef);
+        hipLaunchKernelGGL(k_gram<2>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, gh);
+    hipLaunchKernelGGL(k_ls_solve, dim3(n_regions), dim3(64), 0, s, gh, s_eff, drop, coef);
 }
 
 // x = dab + sum_j a_j y_j on each region, y_j = W.c[j + 1] (outputs).

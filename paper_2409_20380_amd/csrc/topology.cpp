@@ -5,8 +5,8 @@
 // nodes that are close in space are close in memory.
 // Element order: by the lowest internal id among the element's vertices,
 // ties broken by the Morton code of the centroid.  Consecutive runs of
-// patch_elems elements form a patch; a patch is processed by one 64-wide
-// wavefront (up to two elements per lane) that stages the patch's nodes in LDS.  Each patch lists its nodes
+// patch_elems elements form a patch; a patch is processed by one workgroup
+// (one element per thread) that stages the patch's nodes in LDS.  Each patch lists its nodes
 // (vertices first, so the geometry gather touches a prefix only).  Each
 // (patch, node) pair writes its partial result to its own slot; the slots of a
 // node are contiguous and in patch order, which fixes the summation order and
@@ -61,7 +61,7 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     if (N <= 0 || E <= 0) return "mesh must have nodes and elements";
     if (N >= (int64_t)1 << 31 || E >= (int64_t)1 << 31) return "mesh too large for 32-bit ids";
     if (n_mat <= 0 || n_mat > 65535) return "n_mat must be in [1, 65535]";
-    if (patch_elems <= 0 || patch_elems > kMaxPatchElems) return "patch_elems must be in [1, 128]";
+    if (patch_elems <= 0 || patch_elems > kMaxPatchElems) return "patch_elems must be in [1, 256]";
     T = Topology();
     T.n_nodes = N;
     T.n_elems = E;

@@ -11,7 +11,7 @@ namespace ebe {
 // Bit set on a patch-node entry when that patch is the first (owner) patch of
 // the node: the owner writes per-node values that every touching patch computes.
 constexpr uint32_t kOwnerBit = 0x80000000u;
-constexpr int kMaxPatchElems = 128;  // at most two elements per lane of a 64-wide wavefront
+constexpr int kMaxPatchElems = 256;  // one element per thread of a 256-thread workgroup
 
 // Element record used by the kernels: ten patch-local node indices (vertices
 // first, then edges in the conn order), the material id and one pad word.

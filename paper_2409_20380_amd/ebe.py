@@ -127,7 +127,7 @@ class Solver:
     """One handle of the library: a mesh, its state and its history."""
 
     def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
-                 max_iter=10000, drop_tol=1e-6, region_nodes=512, patch_elems=128, chunk_iters=0, stream=None):
+                 max_iter=10000, drop_tol=1e-6, region_nodes=512, patch_elems=256, chunk_iters=0, stream=None):
         import torch
         L = lib()
         cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol,

@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--timing-every", type=int, default=8, help="bracket every n-th matvec launch with events")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.json"))
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.txt"))
     ap.add_argument("--patch-elems", type=int, default=256, help="elements per EBE patch (1..256)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB device-to-device once (counter calibration)")
@@ -150,11 +150,9 @@ def main():
     launch_bytes = bpe * mesh.n_elems
     achieved = launch_bytes / (ebe_ms * 1e-3) / 1e9 if ebe_ms > 0 else 0.0
     traffic = None
-    if os.path.exists(args.traffic_json):
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        if tj.get("workload") == wl.name and tj.get("kernel_source_sha") == kernel_source_sha():
-            traffic = tj.get("bytes_per_launch")
+    tj = read_kv(args.traffic_file)
+    if tj.get("workload") == wl.name and tj.get("kernel_source_sha") == kernel_source_sha():
+        traffic = float(tj["bytes_per_launch"])
 
     out = {
         "metric": "DOF*steps/s at rel. residual 1e-8",
@@ -179,6 +177,7 @@ def main():
         "roofline": {"kernel": "k_ebe<PCG> (fused direction update + EBE matvec + (p,Ap))",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy",
                      "bytes_per_launch": launch_bytes, "mean_launch_ms": ebe_ms, "timed_launches": n_timed},
     }
     sol.close()
@@ -186,6 +185,18 @@ def main():
         log(f"CPU baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(wl_run, mesh, em, mat, fx, regions, wave, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def read_kv(path: str) -> dict:
+    """key = value lines (comments with #) of a profile summary."""
+    out = {}
+    if os.path.exists(path):
+        for line in open(path):
+            line = line.strip()
+            if line and not line.startswith("#") and "=" in line:
+                k, v = line.split("=", 1)
+                out[k.strip()] = v.strip()
+    return out
 
 
 def kernel_source_sha() -> str:

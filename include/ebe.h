@@ -194,7 +194,8 @@ int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int3
 int ebe_sync(ebe_handle* h);
 
 /* Kernel timing: when enabled, every n-th launch of the element-by-element
- * PCG matvec kernel is bracketed by HIP events on the handle's stream.
+ * PCG matvec kernel is bracketed by HIP events on the handle's stream (only
+ * trips that certainly run: index + 3 below the previous solve's count).
  * ebe_kernel_time returns the number of timed launches and their mean
  * duration in milliseconds since the last reset. */
 int ebe_set_kernel_timing(ebe_handle* h, int32_t every_n);

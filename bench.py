@@ -1,5 +1,5 @@
 #!/usr/bin/env python
-"""Throughput of the plain FP64 method on one MI355X.
+"""Throughput of the method on one MI355X.
 
 Workload: layered elastic box of 64 x 64 x 32 cubic cells (2.5 m), each cell
 split into 6 straight 10-node tetrahedra: 1,081,665 nodes, 3,244,995 dof,
@@ -12,6 +12,11 @@ nodes); 3x3 block-Jacobi PCG to relative residual 1e-8.
 One bench step = one full time step (right-hand side, predictor, PCG refine,
 Newmark update) on inputs resident in HBM.  Prints ONE JSON line on stdout;
 progress goes to stderr.
+
+Other forms: --precision fp32|bf16 runs the refine as a flexible FP64 outer
+PCG preconditioned by an inner FP32-arithmetic PCG (vectors FP32, or p and z
+in BF16); --workload large runs the 128 x 128 x 64 cell mesh (25.6M dof,
+300 steps).  The default (plain mesh, FP64) is the headline line.
 """
 from __future__ import annotations
 
@@ -85,6 +90,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.txt"))
     ap.add_argument("--patch-elems", type=int, default=256, help="elements per EBE patch (1..256)")
+    ap.add_argument("--workload", choices=["plain", "large"], default="plain")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
+                    help="fp64: plain PCG; fp32/bf16: flexible FP64 PCG with an inner low-precision PCG")
+    ap.add_argument("--inner-iters", type=int, default=0, help="inner PCG trips per outer trip (0: library default)")
+    ap.add_argument("--inner-tol", type=float, default=0.0, help="inner relative tolerance (0: library default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB device-to-device once (counter calibration)")
     args = ap.parse_args()
@@ -102,7 +112,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = inputs.PLAIN
+    wl = inputs.WORKLOADS[args.workload]
+    prec = {"fp64": ebe.PREC_FP64, "fp32": ebe.PREC_FP32, "bf16": ebe.PREC_BF16}[args.precision]
     nt = args.warmup + args.steps
     wl_run = inputs.Workload(wl.name, cells=wl.cells, h=wl.h, dt=wl.dt, nt=nt, s=wl.s, tol=wl.tol,
                              seed=wl.seed, region_block=wl.region_block)
@@ -110,7 +121,8 @@ def main():
     dof = 3 * mesh.n_nodes
     log(f"mesh {wl.cells}: {mesh.n_nodes} nodes, {dof} dof, {mesh.n_elems} elements")
     aR, bR = wl.rayleigh
-    sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems)
+    sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems, precision=prec,
+                     inner_iters=args.inner_iters, inner_tol=args.inner_tol)
     t0 = time.time()
     sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
     sizes = sol.sizes()
@@ -131,12 +143,13 @@ def main():
             log(f"warmup step {it}: {st.iters} iters, res_true {st.res_true:.2e}")
 
     sol.set_kernel_timing(args.timing_every)
-    iters, res = [], []
+    iters, res, inner = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(args.warmup + 1, nt + 1):
         st = sol.step(base_acc=wave[it])
         iters.append(st.iters)
+        inner.append(st.inner_iters)
         res.append(st.res_true)
         if st.status != 0:
             raise RuntimeError(f"step {it} did not converge")
@@ -146,12 +159,14 @@ def main():
     log(f"timed {args.steps} steps in {elapsed:.3f} s; mean iters {np.mean(iters):.1f}; "
         f"matvec {ebe_ms * 1e3:.1f} us over {n_timed} timed launches")
 
+    ecfg = sol.effective_config()
     bpe = ebe_pcg_bytes_per_element(mesh.n_nodes, mesh.n_elems)
-    launch_bytes = bpe * mesh.n_elems
+    launch_bytes = bpe * mesh.n_elems   # the timed launch is the FP64 (outer) matvec in every form
     achieved = launch_bytes / (ebe_ms * 1e-3) / 1e9 if ebe_ms > 0 else 0.0
     traffic = None
     tj = read_kv(args.traffic_file)
-    if tj.get("workload") == wl.name and tj.get("kernel_source_sha") == kernel_source_sha():
+    if (tj.get("workload") == wl.name and tj.get("precision", "fp64") == args.precision
+            and tj.get("kernel_source_sha") == kernel_source_sha()):
         traffic = float(tj["bytes_per_launch"])
 
     out = {
@@ -165,12 +180,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else f"f64 outer / {args.precision} inner",
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": list(wl.cells), "nodes": mesh.n_nodes, "dof": dof,
                    "elements": mesh.n_elems, "dt": wl.dt, "snapshots": wl.s, "tol": wl.tol,
-                   "predictor": "AB4 + regional snapshot map", "timed_steps": f"{args.warmup + 1}-{nt}"},
+                   "predictor": "AB4 + regional snapshot map", "timed_steps": f"{args.warmup + 1}-{nt}",
+                   "refine": ("block-Jacobi PCG, FP64" if args.precision == "fp64" else
+                              f"flexible FP64 PCG, inner {args.precision} PCG ({ecfg.inner_iters} trips, "
+                              f"tol {ecfg.inner_tol:g})")},
         "cg_iters_per_step": float(np.mean(iters)),
+        "inner_iters_per_step": float(np.mean(inner)),
         "cg_iters_min_max": [int(np.min(iters)), int(np.max(iters))],
         "max_true_rel_residual": float(np.max(res)),
         "ebe_matvec_hbm_gbs": achieved,
@@ -181,7 +200,7 @@ def main():
                      "bytes_per_launch": launch_bytes, "mean_launch_ms": ebe_ms, "timed_launches": n_timed},
     }
     sol.close()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "plain":
         log(f"CPU baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(wl_run, mesh, em, mat, fx, regions, wave, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -62,6 +62,17 @@ extern "C" {
 #define EBE_PRED_AB4 1       /* Adams-Bashforth 4-step estimate (Sec. 3.2) */
 #define EBE_PRED_SNAPSHOT 2  /* AB4 + regional snapshot map (Sec. 3.2) */
 
+/* Precision of the refinement.  FP64: Algorithm 1 in FP64.  FP32 / BF16: a
+ * flexible outer PCG in FP64 (residual, dot products, update; Polak-Ribiere
+ * beta because the preconditioner varies) whose preconditioner is an inner
+ * 3x3 block-Jacobi PCG with an FP32 element-by-element matvec and FP32
+ * arithmetic, its direction and preconditioned-residual vectors stored in
+ * FP32 or BF16; the outer stop test is the same relative FP64 residual.  The
+ * predictor's least squares stays FP64 in every mode. */
+#define EBE_PREC_FP64 0
+#define EBE_PREC_FP32 1
+#define EBE_PREC_BF16 2
+
 typedef struct ebe_handle ebe_handle;
 
 typedef struct {
@@ -72,6 +83,8 @@ typedef struct {
     double drop_tol;        /* snapshot column kept only if its part orthogonal to the
                                earlier kept columns has norm >= drop_tol * its norm
                                (<= 0: 1e-6) */
+    double inner_tol;       /* mixed precision: relative residual target of each inner
+                               solve (<= 0: 1e-2) */
     int32_t max_iter;       /* PCG iteration cap per solve (<= 0: 10000) */
     int32_t s;              /* snapshot window: number of input columns, 0..32 */
     int32_t predictor;      /* EBE_PRED_* */
@@ -80,14 +93,17 @@ typedef struct {
     int32_t patch_elems;    /* elements per EBE patch, 1..256 (<= 0: 256) */
     int32_t chunk_iters;    /* PCG iterations enqueued between convergence checks
                                (<= 0: adaptive) */
-    int32_t reserved[6];
+    int32_t precision;      /* EBE_PREC_*: how Algorithm 1 is run (see below) */
+    int32_t inner_iters;    /* mixed precision: inner PCG trips per outer trip at most
+                               (<= 0: 12) */
+    int32_t reserved[4];
 } ebe_config;
 
 typedef struct {
     int32_t iters;      /* PCG loop trips (q = A p products), the r0 product excluded */
     int32_t restarts;   /* restarts after a true-residual check failed */
     int32_t status;     /* EBE_OK or EBE_NOT_CONVERGED */
-    int32_t pad;
+    int32_t inner_iters;  /* mixed precision: inner PCG trips summed over the solve */
     double res0;        /* ||b - A x-bar|| / ||b|| */
     double res_rec;     /* recursive residual at exit, relative */
     double res_true;    /* ||b - A x|| / ||b|| recomputed at exit */
@@ -100,7 +116,7 @@ typedef struct {
     int32_t iters;
     int32_t restarts;
     int32_t status;
-    int32_t pad;
+    int32_t inner_iters;
     double res0, res_rec, res_true, bnorm;
 } ebe_step_stats;
 
@@ -169,8 +185,9 @@ int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* 
  * (may be NULL).  The state is not modified. */
 int ebe_predict(ebe_handle* h, const double* f_next, double* dxbar, int32_t* s_eff);
 
-/* Algorithm 1: solve A_bc x = b to ||b - A x|| / ||b|| < tol starting from the
- * guess in x (overwritten with the solution).  If ||b|| = 0, x = 0 with zero
+/* Algorithm 1 (or its mixed-precision form, cfg.precision): solve A_bc x = b to
+ * ||b - A x|| / ||b|| < tol starting from the guess in x (overwritten with the
+ * solution).  If ||b|| = 0, x = 0 with zero
  * iterations.  Returns NOT_CONVERGED when max_iter is reached, NONFINITE if a
  * scalar of the iteration is not finite. */
 int ebe_refine(ebe_handle* h, const double* b, double* x, ebe_solve_stats* stats);
@@ -204,6 +221,10 @@ int ebe_kernel_time(ebe_handle* h, int64_t* launches, double* mean_ms);
 /* Sizes used for roofline accounting of one PCG iteration: n_nodes, n_elems,
  * n_patch_nodes (sum over patches of the nodes each patch touches), patches. */
 int ebe_sizes(ebe_handle* h, int64_t* n_nodes, int64_t* n_elems, int64_t* n_patch_nodes, int64_t* n_patches);
+
+/* The configuration in effect (defaults filled in for fields given as <= 0).
+ * out: host struct written by the call.  EBE_E_INVALID_ARG if out is NULL. */
+int ebe_get_config(ebe_handle* h, ebe_config* out);
 
 #ifdef __cplusplus
 }

@@ -73,7 +73,15 @@ struct ebe_handle {
     DevScalars* sc = nullptr;
     DevScalars* sc_host = nullptr;
     double* pap_part = nullptr;   // (p, A p) partials of the matvec grid
-    double* res_part = nullptr;   // two slots of [3][res_grid] residual partials
+    double* res_part = nullptr;   // two slots of [kResArrays][res_grid] residual partials
+    // mixed precision (inner solve in FP32 arithmetic, vectors in FP32 / BF16)
+    void *r_in = nullptr, *e_in = nullptr, *z_in = nullptr, *p_in[2] = {nullptr, nullptr}, *q_in = nullptr;
+    void* binv_in = nullptr;
+    double* r_prev = nullptr;
+    DevScalars* sc_in = nullptr;
+    double* pap_in = nullptr;
+    double* res_in = nullptr;
+    int par_in = 0;
     // kernel timing
     int timing_every = 0;
     int64_t pcg_launches = 0;
@@ -198,6 +206,35 @@ void sync_stream(ebe_handle* h) {
     if (!h->ev_pending.empty()) harvest_timing(h, true);
 }
 
+// Statistics and status of a finished solve from the scalars read back last.
+int finish_solve(ebe_handle* h, double* x, int done, ebe_solve_stats* st) {
+    const DevScalars& S = *h->sc_host;
+    if (done == DONE_ZERO_RHS) {
+        launch_zero(h->stream, h->n3(), x);
+        check_launch();
+    }
+    if (st) {
+        st->iters = S.iters;
+        st->restarts = S.restarts;
+        st->inner_iters = S.inner_iters;
+        st->res0 = S.res0;
+        st->bnorm = S.bnorm;
+        st->res_rec = S.bnorm > 0 ? std::sqrt(S.rr) / S.bnorm : 0.0;
+        st->res_true = S.bnorm > 0 ? S.res_true : 0.0;
+        st->status = (done == DONE_MAXITER) ? EBE_NOT_CONVERGED : EBE_OK;
+    }
+    if (done == DONE_NONFINITE) {
+        h->err = "non-finite value in the PCG iteration";
+        return EBE_E_NONFINITE;
+    }
+    h->last_iters = S.iters;
+    if (done == DONE_MAXITER) {
+        h->err = "PCG reached max_iter";
+        return EBE_NOT_CONVERGED;
+    }
+    return EBE_OK;
+}
+
 // Algorithm 1 on internal-order vectors: b, x (guess in, solution out).
 // Trips are enqueued in chunks; a device-side stop flag makes the remaining
 // kernels of a chunk return at once, and the host reads the scalars once per
@@ -209,7 +246,7 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
     const int max_iter = h->cfg.max_iter;
     const int g_res = res_grid(h->T.n_nodes);
     const int g_pap = pcg_ebe_grid(h->dp);
-    auto slot = [&](int j) { return h->res_part + (size_t)(j & 1) * 3 * g_res; };
+    auto slot = [&](int j) { return h->res_part + (size_t)(j & 1) * kResArrays * g_res; };
     launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
     launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(0), 0);
     check_launch();
@@ -228,15 +265,17 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
                 e1 = take_event(h);
                 HIPCHK(hipEventRecord(e0, s));
             }
-            launch_ebe_pcg(s, h->dp, h->z, pprev, pcur, h->cM, h->cK, h->qbuf, h->sc, slot(j), g_res, h->pap_part,
-                           j, max_iter, tol);
+            PcgLaunch L{&h->dp, PREC_FP64, false, h->z, pprev, pcur, h->qbuf, h->cM, h->cK, h->sc, nullptr,
+                        slot(j), g_res, h->pap_part, j, max_iter, tol};
+            launch_ebe_pcg(s, L);
             if (timed) {
                 HIPCHK(hipEventRecord(e1, s));
                 h->ev_pending.emplace_back(e0, e1);
             }
             h->pcg_launches++;
-            launch_pcg_update(s, h->dn, h->qbuf, pcur, h->binv6, x, h->r, h->z, h->sc, h->pap_part, g_pap,
-                              slot(j + 1), j);
+            UpdLaunch U{&h->dn, PREC_FP64, h->qbuf, pcur, h->binv6, x, h->r, h->z, h->sc, nullptr, h->pap_part, g_pap,
+                        slot(j + 1), j, nullptr};
+            launch_pcg_update(s, U);
             h->par ^= 1;
         }
         // true-residual check (runs on the device only once the loop stopped)
@@ -254,30 +293,87 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
         }
         break;
     }
-    const DevScalars& S = *h->sc_host;
-    if (done == DONE_ZERO_RHS) {
-        launch_zero(s, h->n3(), x);
+    return finish_solve(h, x, done, st);
+}
+
+// Mixed-precision refinement: flexible FP64 outer PCG whose preconditioner is
+// an inner block-Jacobi PCG in FP32 arithmetic (vectors stored in FP32 or BF16).
+// Outer trip j: inner init (outer stop test on r, r_in = float(r)), at most
+// inner_iters inner trips (they stop at inner_tol), z = e in FP64 with the
+// partials (z,r), (r,r), (z,r_prev), flexible matvec (Polak-Ribiere beta,
+// p = z + beta p, q = A p), outer update.  All stop tests run on the device;
+// the host reads the scalars once per chunk of outer trips.
+int solve_mixed(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
+    hipStream_t s = h->stream;
+    const double tol = h->cfg.tol;
+    const int max_iter = h->cfg.max_iter;
+    const int prec = h->cfg.precision;
+    const int g_res = res_grid(h->T.n_nodes);
+    const int g_pap = pcg_ebe_grid(h->dp);
+    auto slot = [&](int j) { return h->res_part + (size_t)(j & 1) * kResArrays * g_res; };
+    auto islot = [&](int i) { return h->res_in + (size_t)(i & 1) * kResArrays * g_res; };
+    launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
+    launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(0), 0);
+    check_launch();
+    int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(1, h->last_iters - 1);
+    int done = DONE_RUNNING;
+    int j = 0;
+    for (int round = 0;; ++round) {
+        for (int k = 0; k < chunk; ++k, ++j) {
+            launch_inner_init(s, prec, h->dn, h->r, h->binv_in, h->r_in, h->e_in, h->z_in, h->sc, slot(j), j,
+                              max_iter, tol, h->sc_in, islot(0));
+            for (int i = 0; i < h->cfg.inner_iters; ++i) {
+                void* pprev = h->p_in[h->par_in];
+                void* pcur = h->p_in[h->par_in ^ 1];
+                PcgLaunch L{&h->dp, prec, false, h->z_in, pprev, pcur, h->q_in, h->cM, h->cK, h->sc_in, h->sc,
+                            islot(i), g_res, h->pap_in, i, h->cfg.inner_iters, h->cfg.inner_tol};
+                launch_ebe_pcg(s, L);
+                UpdLaunch U{&h->dn, prec, h->q_in, pcur, h->binv_in, h->e_in, h->r_in, h->z_in, h->sc_in, h->sc,
+                            h->pap_in, g_pap, islot(i + 1), i, &h->sc->inner_iters};
+                launch_pcg_update(s, U);
+                h->par_in ^= 1;
+            }
+            launch_outer_z(s, h->dn, h->e_in, h->r, h->r_prev, h->z, h->sc, slot(j), j);
+            double* pprev = h->p[h->par];
+            double* pcur = h->p[h->par ^ 1];
+            bool timed = h->timing_every > 0 && (h->pcg_launches % h->timing_every) == 0 && j + 2 < h->last_iters;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timed) {
+                e0 = take_event(h);
+                e1 = take_event(h);
+                HIPCHK(hipEventRecord(e0, s));
+            }
+            PcgLaunch L{&h->dp, PREC_FP64, true, h->z, pprev, pcur, h->qbuf, h->cM, h->cK, h->sc, nullptr, slot(j),
+                        g_res, h->pap_part, j, max_iter, tol};
+            launch_ebe_pcg(s, L);
+            if (timed) {
+                HIPCHK(hipEventRecord(e1, s));
+                h->ev_pending.emplace_back(e0, e1);
+            }
+            h->pcg_launches++;
+            launch_outer_update(s, h->dn, h->qbuf, pcur, x, h->r, h->r_prev, h->sc, h->pap_part, g_pap, slot(j + 1),
+                                j);
+            h->par ^= 1;
+        }
+        launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf, h->sc);
+        launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(j), 1);
+        launch_check_finalize(s, h->sc, slot(j), g_res, j, tol);
         check_launch();
+        HIPCHK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        sync_stream(h);
+        done = h->sc_host->done;
+        if (done == DONE_RUNNING) {
+            chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : 1;
+            if (round > 100000) throw HipError{"PCG loop did not terminate"};
+            continue;
+        }
+        break;
     }
-    if (st) {
-        st->iters = S.iters;
-        st->restarts = S.restarts;
-        st->res0 = S.res0;
-        st->bnorm = S.bnorm;
-        st->res_rec = S.bnorm > 0 ? std::sqrt(S.rr) / S.bnorm : 0.0;
-        st->res_true = S.bnorm > 0 ? S.res_true : 0.0;
-        st->status = (done == DONE_MAXITER) ? EBE_NOT_CONVERGED : EBE_OK;
-    }
-    if (done == DONE_NONFINITE) {
-        h->err = "non-finite value in the PCG iteration";
-        return EBE_E_NONFINITE;
-    }
-    h->last_iters = S.iters;
-    if (done == DONE_MAXITER) {
-        h->err = "PCG reached max_iter";
-        return EBE_NOT_CONVERGED;
-    }
-    return EBE_OK;
+    return finish_solve(h, x, done, st);
+}
+
+int run_solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
+    return h->cfg.precision == EBE_PREC_FP64 ? solve(h, b, x, st) : solve_mixed(h, b, x, st);
 }
 
 int snapshot_columns(const ebe_handle* h, int n) {
@@ -320,7 +416,7 @@ void rhs_into(ebe_handle* h, const double* f_int, const double* g, double* b) {
 
 extern "C" {
 
-const char* ebe_version(void) { return "ebe-ddpcg 0.1 (gfx950, FP64)"; }
+const char* ebe_version(void) { return "ebe-ddpcg 0.2 (gfx950; FP64, mixed FP32/BF16 inner PCG)"; }
 
 const char* ebe_last_error(const ebe_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
 
@@ -333,15 +429,18 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     *out = nullptr;
     ebe_config c = *cfg;
     if (!(c.dt > 0) || !(c.tol > 0) || c.s < 0 || c.s > 32 || c.predictor < 0 || c.predictor > 2 ||
-        c.rayleigh_alpha < 0 || c.rayleigh_beta < 0 || c.patch_elems > kMaxPatchElems) {
+        c.rayleigh_alpha < 0 || c.rayleigh_beta < 0 || c.patch_elems > kMaxPatchElems || c.precision < 0 ||
+        c.precision > 2) {
         g_create_error = "invalid configuration (need dt > 0, tol > 0, 0 <= s <= 32, predictor in 0..2, "
-                         "non-negative damping, patch_elems <= 256)";
+                         "non-negative damping, patch_elems <= 256, precision in 0..2)";
         return EBE_E_INVALID_ARG;
     }
     if (c.max_iter <= 0) c.max_iter = 10000;
     if (c.drop_tol <= 0) c.drop_tol = 1e-6;
     if (c.region_nodes <= 0) c.region_nodes = 512;
     if (c.patch_elems <= 0) c.patch_elems = kMaxPatchElems;
+    if (c.inner_iters <= 0) c.inner_iters = 12;
+    if (c.inner_tol <= 0) c.inner_tol = 1e-2;
     ebe_handle* h = new (std::nothrow) ebe_handle();
     if (!h) {
         g_create_error = "out of memory";
@@ -427,12 +526,26 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->gh = h->alloc<double>((size_t)kGhStride * T.n_regions);
         h->sc = h->alloc<DevScalars>(1);
         h->pap_part = h->alloc<double>(pcg_ebe_grid(h->dp));
-        h->res_part = h->alloc<double>(2 * 3 * (size_t)res_grid(N));
+        h->res_part = h->alloc<double>(2 * kResArrays * (size_t)res_grid(N));
+        if (h->cfg.precision != EBE_PREC_FP64) {
+            h->r_in = h->alloc<float>(n3);
+            h->e_in = h->alloc<float>(n3);
+            h->z_in = h->alloc<float>(n3);         // FP32 or BF16 storage (BF16 uses half)
+            h->p_in[0] = h->alloc<float>(n3);
+            h->p_in[1] = h->alloc<float>(n3);
+            h->q_in = h->alloc<float>(3 * PN);
+            h->binv_in = h->alloc<float>(6 * N);
+            h->r_prev = h->alloc<double>(n3);
+            h->sc_in = h->alloc<DevScalars>(1);
+            h->pap_in = h->alloc<double>(pcg_ebe_grid(h->dp));
+            h->res_in = h->alloc<double>(2 * kResArrays * (size_t)res_grid(N));
+        }
         if (!h->sc_host) HIPCHK(hipHostMalloc((void**)&h->sc_host, sizeof(DevScalars), hipHostMallocDefault));
         HIPCHK(hipMemsetAsync(h->sc, 0, sizeof(DevScalars), s));
         // block-Jacobi inverse of A_bc
         launch_ebe_diag(s, h->dp, h->cM, h->cK, h->qbuf);
         launch_diag_finalize(s, h->dn, h->qbuf, h->binv6);
+        if (h->binv_in) launch_to_f32(s, 6 * N, h->binv6, static_cast<float*>(h->binv_in));
         // rest state
         launch_zero(s, n3, h->u);
         launch_zero(s, n3, h->a);
@@ -440,6 +553,11 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         launch_zero(s, (int64_t)(h->cfg.s + 1) * n3, h->ring);
         launch_zero(s, n3, h->p[0]);
         launch_zero(s, n3, h->p[1]);
+        if (h->p_in[0]) {
+            HIPCHK(hipMemsetAsync(h->p_in[0], 0, n3 * sizeof(float), s));
+            HIPCHK(hipMemsetAsync(h->p_in[1], 0, n3 * sizeof(float), s));
+            HIPCHK(hipMemsetAsync(h->sc_in, 0, sizeof(DevScalars), s));
+        }
         check_launch();
         HIPCHK(hipStreamSynchronize(s));
         h->head = 0;
@@ -538,7 +656,7 @@ int ebe_refine(ebe_handle* h, const double* b, double* x, ebe_solve_stats* stats
         to_internal(h, b, h->t0);
         to_internal(h, x, h->t1);
         check_launch();
-        int rc = solve(h, h->t0, h->t1, stats);
+        int rc = run_solve(h, h->t0, h->t1, stats);
         to_user(h, h->t1, x);
         check_launch();
         return rc;
@@ -558,7 +676,7 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
         const int n = h->it + 1;
         int s_eff = predict_into(h, h->x);
         ebe_solve_stats st{};
-        int rc = solve(h, h->b, h->x, &st);
+        int rc = run_solve(h, h->b, h->x, &st);
         if (rc < 0) return rc;
         double* slot = h->cfg.s >= 1 ? h->ring_slot((n - 1) % (h->cfg.s + 1)) : nullptr;
         launch_newmark(s, h->n3(), h->cfg.dt, h->x, h->dab, h->u, h->vslot(0), h->vslot(3), h->a, slot);
@@ -570,6 +688,7 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
             stats->s_eff = s_eff;
             stats->iters = st.iters;
             stats->restarts = st.restarts;
+            stats->inner_iters = st.inner_iters;
             stats->status = st.status;
             stats->res0 = st.res0;
             stats->res_rec = st.res_rec;
@@ -665,6 +784,14 @@ int ebe_sizes(ebe_handle* h, int64_t* n_nodes, int64_t* n_elems, int64_t* n_patc
         if (n_elems) *n_elems = h->T.n_elems;
         if (n_patch_nodes) *n_patch_nodes = (int64_t)h->T.patch_nodes.size();
         if (n_patches) *n_patches = h->T.n_patches;
+        return EBE_OK;
+    });
+}
+
+int ebe_get_config(ebe_handle* h, ebe_config* out) {
+    return guarded(h, [&]() -> int {
+        need_ptr(out, "out");
+        *out = h->cfg;
         return EBE_OK;
     });
 }

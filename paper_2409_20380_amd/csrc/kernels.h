@@ -21,10 +21,19 @@ struct DevScalars {
     int32_t restarts;
     int32_t checked;  // true residual evaluated since the loop stopped
     int32_t cycle_start;  // trip index at which the current CG cycle began (beta = 0 there)
-    int32_t pad;
+    int32_t inner_iters;  // mixed precision: inner trips summed over the solve
 };
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_NONFINITE = 2, DONE_MAXITER = 3, DONE_ZERO_RHS = 4 };
+
+// Precision of a PCG solve: FP64 throughout, or FP32 arithmetic with the
+// direction and preconditioned-residual vectors stored in FP32 or BF16.
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+
+// 16-bit brain float storage (upper half of an IEEE binary32).
+struct bf16_t {
+    uint16_t bits;
+};
 
 // Device copies of the topology arrays used by the element kernels.
 struct DevPatches {
@@ -51,6 +60,7 @@ constexpr int kMaxCols = 33;    // s <= 32 input columns plus the query
 constexpr int kEbeWaves = 4;        // wavefronts per EBE workgroup (one patch per workgroup)
 constexpr int kMaxPcgGrid = 512;    // persistent workgroups of the PCG matvec (multiple of 8)
 constexpr int kMaxResGrid = 1024;   // workgroups of the node-wise reduction kernels
+constexpr int kResArrays = 4;       // partial arrays per slot: (z,r), (r,r), (b,b), (z,r_prev)
 struct ColPtrs {
     const double* c[kMaxCols];
 };
@@ -64,9 +74,24 @@ void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool 
 // PCG trip j, matvec part: stop test on the incoming residual partials, beta,
 // p_cur = z + beta p_prev, qbuf = A_e p_cur and (p, A p) partials.
 int pcg_ebe_grid(const DevPatches& P);
-void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const double* p_prev, double* p_cur,
-                    double cm, double ck, double* qbuf, DevScalars* sc, const double* res_part, int g_res,
-                    double* pap_part, int j, int max_iter, double tol);
+struct PcgLaunch {
+    const DevPatches* P;
+    int prec;            // PREC_*: compute / storage types of z, p_prev, p_cur, qbuf
+    bool flexible;       // FP64 only: Polak-Ribiere beta (needs the (z, r_prev) partials)
+    const void* z;
+    const void* p_prev;
+    void* p_cur;
+    void* qbuf;
+    double cm, ck;
+    DevScalars* sc;
+    const DevScalars* outer;   // inner solves: stop when the outer solve stopped
+    const double* res_part;
+    int g_res;
+    double* pap_part;
+    int j, max_iter;
+    double tol;
+};
+void launch_ebe_pcg(hipStream_t s, const PcgLaunch& L);
 // Right-hand side operands: M part w1 = a + c1 v - g, K part w2 = c2 v - u.
 void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const double* v, const double* a,
                     double c1, double c2, double g0, double g1, double g2, double* qbuf);
@@ -89,9 +114,33 @@ int res_grid(int64_t n);
 void launch_residual(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, const double* binv6,
                      double* x, double* r, double* z, DevScalars* sc, double* res_part, int mode);
 void launch_check_finalize(hipStream_t s, DevScalars* sc, const double* res_part, int g, int j_next, double tol);
-void launch_pcg_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, const double* binv6,
-                       double* x, double* r, double* z, DevScalars* sc, const double* pap_part, int g_pap,
-                       double* res_part, int j);
+struct UpdLaunch {
+    const DevNodes* N;
+    int prec;
+    const void* qbuf;
+    const void* p;
+    const void* binv;
+    void* x;
+    void* r;
+    void* z;
+    DevScalars* sc;
+    const DevScalars* outer;
+    const double* pap_part;
+    int g_pap;
+    double* res_part;
+    int j;
+    int32_t* inner_count;   // if set, incremented once per trip that ran
+};
+void launch_pcg_update(hipStream_t s, const UpdLaunch& L);
+// Mixed precision (flexible FP64 outer PCG with an inner PCG preconditioner).
+void launch_inner_init(hipStream_t s, int prec, const DevNodes& N, const double* r64, const void* binv, void* r,
+                       void* e, void* z, DevScalars* outer, const double* outer_part, int j, int max_iter, double tol,
+                       DevScalars* sc_in, double* in_part);
+void launch_outer_z(hipStream_t s, const DevNodes& N, const void* e, const double* r, const double* r_prev, double* z,
+                    const DevScalars* outer, double* part, int j);
+void launch_outer_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, double* x, double* r,
+                         double* r_prev, DevScalars* sc, const double* pap_part, int g_pap, double* part, int j);
+void launch_to_f32(hipStream_t s, int64_t n, const double* in, float* out);
 
 // ---- predictor and time integration (all lengths in dofs, 3N)
 void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const double* v2, const double* v3,

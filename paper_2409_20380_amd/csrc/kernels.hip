@@ -68,30 +68,50 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-struct Geo {
-    double g[4][3];
-    double V;
+// Storage conversions.  bf16_t holds the upper 16 bits of an IEEE binary32;
+// rounding to it is round-to-nearest-even on the dropped 16 bits.
+template <class T, class S>
+__device__ __forceinline__ T from_storage(S v) { return (T)v; }
+template <>
+__device__ __forceinline__ float from_storage<float, bf16_t>(bf16_t v) {
+    return __uint_as_float((uint32_t)v.bits << 16);
+}
+template <class S, class T>
+__device__ __forceinline__ S to_storage(T v) { return (S)v; }
+template <>
+__device__ __forceinline__ bf16_t to_storage<bf16_t, float>(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_t{(uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u))};
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return bf16_t{(uint16_t)(u >> 16)};
+}
+
+template <class T>
+struct GeoT {
+    T g[4][3];
+    T V;
 };
 
 // Barycentric gradients of a straight tetrahedron: rows of J^{-1} with
 // J = [x1-x0, x2-x0, x3-x0]; grad L0 = -(grad L1 + grad L2 + grad L3).
-__device__ __forceinline__ void tet_geo(const double* x0, const double* x1, const double* x2, const double* x3,
-                                        Geo& G) {
-    double a0 = x1[0] - x0[0], a1 = x2[0] - x0[0], a2 = x3[0] - x0[0];
-    double b0 = x1[1] - x0[1], b1 = x2[1] - x0[1], b2 = x3[1] - x0[1];
-    double c0 = x1[2] - x0[2], c1 = x2[2] - x0[2], c2 = x3[2] - x0[2];
-    double m00 = b1 * c2 - b2 * c1, m01 = a2 * c1 - a1 * c2, m02 = a1 * b2 - a2 * b1;
-    double m10 = b2 * c0 - b0 * c2, m11 = a0 * c2 - a2 * c0, m12 = a2 * b0 - a0 * b2;
-    double m20 = b0 * c1 - b1 * c0, m21 = a1 * c0 - a0 * c1, m22 = a0 * b1 - a1 * b0;
-    double det = a0 * m00 + a1 * m10 + a2 * m20;
-    double id = 1.0 / det;
+template <class T>
+__device__ __forceinline__ void tet_geo(const T* x0, const T* x1, const T* x2, const T* x3, GeoT<T>& G) {
+    T a0 = x1[0] - x0[0], a1 = x2[0] - x0[0], a2 = x3[0] - x0[0];
+    T b0 = x1[1] - x0[1], b1 = x2[1] - x0[1], b2 = x3[1] - x0[1];
+    T c0 = x1[2] - x0[2], c1 = x2[2] - x0[2], c2 = x3[2] - x0[2];
+    T m00 = b1 * c2 - b2 * c1, m01 = a2 * c1 - a1 * c2, m02 = a1 * b2 - a2 * b1;
+    T m10 = b2 * c0 - b0 * c2, m11 = a0 * c2 - a2 * c0, m12 = a2 * b0 - a0 * b2;
+    T m20 = b0 * c1 - b1 * c0, m21 = a1 * c0 - a0 * c1, m22 = a0 * b1 - a1 * b0;
+    T det = a0 * m00 + a1 * m10 + a2 * m20;
+    T id = T(1) / det;
     G.g[1][0] = m00 * id; G.g[1][1] = m01 * id; G.g[1][2] = m02 * id;
     G.g[2][0] = m10 * id; G.g[2][1] = m11 * id; G.g[2][2] = m12 * id;
     G.g[3][0] = m20 * id; G.g[3][1] = m21 * id; G.g[3][2] = m22 * id;
 #pragma unroll
     for (int d = 0; d < 3; ++d) G.g[0][d] = -(G.g[1][d] + G.g[2][d] + G.g[3][d]);
-    G.V = det * (1.0 / 6.0);
+    G.V = det * T(1.0 / 6.0);
 }
+using Geo = GeoT<double>;
 
 // local edge index (4..9) of the vertex pair (k, j)
 __device__ __forceinline__ constexpr int edge_of(int k, int j) {
@@ -99,28 +119,30 @@ __device__ __forceinline__ constexpr int edge_of(int k, int j) {
     return a == 0 ? (b == 1 ? 4 : b == 2 ? 6 : 7) : a == 1 ? (b == 2 ? 5 : 8) : 9;
 }
 
-// f[10][3] = mc * Mhat pm + K pk  (Mhat: mass table in units of rho V/420
-// scaled into mc; K with lamV = ck lam V/20, muV = ck mu V/20).
-__device__ __forceinline__ void element_apply(const double (&pm)[10][3], const double (&pk)[10][3], const Geo& G,
-                                              double lamV, double muV, double mc, double (&f)[10][3]) {
-    // ---- stiffness: vertex stresses (scaled by V/20)
-    double sg[4][6];
+// f = mc * Mhat pm + K pk for one element (Mhat: P2 mass table in units of
+// rho V / 420, scaled into mc; K with lamV = ck lam V/20, muV = ck mu V/20),
+// each node's 3-vector handed to emit(i, f0, f1, f2) as soon as it is formed:
+// the 30 outputs are never all live, which keeps register pressure down.
+template <class T, class Emit>
+__device__ __forceinline__ void element_apply_emit(const T (&pm)[10][3], const T (&pk)[10][3], const GeoT<T>& G,
+                                                   T lamV, T muV, T mc, Emit&& emit) {
+    T sg[4][6];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (j == k) continue;
             const int e = edge_of(k, j);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double d = 4.0 * pk[e][c] - pk[j][c] - 3.0 * pk[k][c];
+                T d = T(4) * pk[e][c] - pk[j][c] - T(3) * pk[k][c];
 #pragma unroll
                 for (int dd = 0; dd < 3; ++dd) H[c][dd] = fma(d, G.g[j][dd], H[c][dd]);
             }
         }
-        double tr = lamV * (H[0][0] + H[1][1] + H[2][2]);
-        double m2 = 2.0 * muV;
+        T tr = lamV * (H[0][0] + H[1][1] + H[2][2]);
+        T m2 = T(2) * muV;
         sg[k][0] = fma(m2, H[0][0], tr);
         sg[k][1] = fma(m2, H[1][1], tr);
         sg[k][2] = fma(m2, H[2][2], tr);
@@ -128,94 +150,10 @@ __device__ __forceinline__ void element_apply(const double (&pm)[10][3], const d
         sg[k][4] = muV * (H[0][2] + H[2][0]);
         sg[k][5] = muV * (H[1][2] + H[2][1]);
     }
-    double S[6];
+    T S[6];
 #pragma unroll
     for (int t = 0; t < 6; ++t) S[t] = (sg[0][t] + sg[1][t]) + (sg[2][t] + sg[3][t]);
-    // vertex forces: (4 sigma_k - S) g_k
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double t[6];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) t[q] = fma(4.0, sg[k][q], -S[q]);
-        const double* g = G.g[k];
-        f[k][0] = t[0] * g[0] + t[3] * g[1] + t[4] * g[2];
-        f[k][1] = t[3] * g[0] + t[1] * g[1] + t[5] * g[2];
-        f[k][2] = t[4] * g[0] + t[5] * g[1] + t[2] * g[2];
-    }
-    // edge forces: 4 ((sigma_k + S) g_j + (sigma_j + S) g_k)
-    double T[4][6];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) T[k][q] = 4.0 * (sg[k][q] + S[q]);
-    constexpr int EV[6][2] = {{0, 1}, {1, 2}, {0, 2}, {0, 3}, {1, 3}, {2, 3}};
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        const int k = EV[m][0], j = EV[m][1];
-        const double* gj = G.g[j];
-        const double* gk = G.g[k];
-        const double* A = T[k];
-        const double* B = T[j];
-        f[4 + m][0] = A[0] * gj[0] + A[3] * gj[1] + A[4] * gj[2] + B[0] * gk[0] + B[3] * gk[1] + B[4] * gk[2];
-        f[4 + m][1] = A[3] * gj[0] + A[1] * gj[1] + A[5] * gj[2] + B[3] * gk[0] + B[1] * gk[1] + B[5] * gk[2];
-        f[4 + m][2] = A[4] * gj[0] + A[5] * gj[1] + A[2] * gj[2] + B[4] * gk[0] + B[5] * gk[1] + B[2] * gk[2];
-    }
-    // ---- consistent mass
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double p0 = pm[0][c], p1 = pm[1][c], p2 = pm[2][c], p3 = pm[3][c];
-        double p4 = pm[4][c], p5 = pm[5][c], p6 = pm[6][c], p7 = pm[7][c], p8 = pm[8][c], p9 = pm[9][c];
-        double Pv = (p0 + p1) + (p2 + p3);
-        double Pe = (p4 + p5) + (p6 + p7) + (p8 + p9);
-        double bv = Pv - 6.0 * Pe;
-        double be = 16.0 * Pe - 6.0 * Pv;
-        f[0][c] = fma(mc, fma(5.0, p0, bv) + 2.0 * (p4 + p6 + p7), f[0][c]);
-        f[1][c] = fma(mc, fma(5.0, p1, bv) + 2.0 * (p4 + p5 + p8), f[1][c]);
-        f[2][c] = fma(mc, fma(5.0, p2, bv) + 2.0 * (p5 + p6 + p9), f[2][c]);
-        f[3][c] = fma(mc, fma(5.0, p3, bv) + 2.0 * (p7 + p8 + p9), f[3][c]);
-        f[4][c] = fma(mc, be + 2.0 * (p0 + p1) + 16.0 * p4 - 8.0 * p9, f[4][c]);
-        f[5][c] = fma(mc, be + 2.0 * (p1 + p2) + 16.0 * p5 - 8.0 * p7, f[5][c]);
-        f[6][c] = fma(mc, be + 2.0 * (p0 + p2) + 16.0 * p6 - 8.0 * p8, f[6][c]);
-        f[7][c] = fma(mc, be + 2.0 * (p0 + p3) + 16.0 * p7 - 8.0 * p5, f[7][c]);
-        f[8][c] = fma(mc, be + 2.0 * (p1 + p3) + 16.0 * p8 - 8.0 * p6, f[8][c]);
-        f[9][c] = fma(mc, be + 2.0 * (p2 + p3) + 16.0 * p9 - 8.0 * p4, f[9][c]);
-    }
-}
-
-// Same operator as element_apply, with each node's 3-vector handed to
-// emit(i, f0, f1, f2) as soon as it is formed: the 30 outputs are never all
-// live, which keeps register pressure (and so occupancy) in check.
-template <class Emit>
-__device__ __forceinline__ void element_apply_emit(const double (&pm)[10][3], const double (&pk)[10][3], const Geo& G,
-                                                   double lamV, double muV, double mc, Emit&& emit) {
-    double sg[4][6];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        double H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (j == k) continue;
-            const int e = edge_of(k, j);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double d = 4.0 * pk[e][c] - pk[j][c] - 3.0 * pk[k][c];
-#pragma unroll
-                for (int dd = 0; dd < 3; ++dd) H[c][dd] = fma(d, G.g[j][dd], H[c][dd]);
-            }
-        }
-        double tr = lamV * (H[0][0] + H[1][1] + H[2][2]);
-        double m2 = 2.0 * muV;
-        sg[k][0] = fma(m2, H[0][0], tr);
-        sg[k][1] = fma(m2, H[1][1], tr);
-        sg[k][2] = fma(m2, H[2][2], tr);
-        sg[k][3] = muV * (H[0][1] + H[1][0]);
-        sg[k][4] = muV * (H[0][2] + H[2][0]);
-        sg[k][5] = muV * (H[1][2] + H[2][1]);
-    }
-    double S[6];
-#pragma unroll
-    for (int t = 0; t < 6; ++t) S[t] = (sg[0][t] + sg[1][t]) + (sg[2][t] + sg[3][t]);
-    double Pv[3], Pe[3];
+    T Pv[3], Pe[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Pv[c] = (pm[0][c] + pm[1][c]) + (pm[2][c] + pm[3][c]);
@@ -225,17 +163,17 @@ __device__ __forceinline__ void element_apply_emit(const double (&pm)[10][3], co
     constexpr int INC[4][3] = {{4, 6, 7}, {4, 5, 8}, {5, 6, 9}, {7, 8, 9}};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        double t[6];
+        T t[6];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) t[q] = fma(4.0, sg[k][q], -S[q]);
-        const double* g = G.g[k];
-        double f[3];
+        for (int q = 0; q < 6; ++q) t[q] = fma(T(4), sg[k][q], -S[q]);
+        const T* g = G.g[k];
+        T f[3];
         f[0] = t[0] * g[0] + t[3] * g[1] + t[4] * g[2];
         f[1] = t[3] * g[0] + t[1] * g[1] + t[5] * g[2];
         f[2] = t[4] * g[0] + t[5] * g[1] + t[2] * g[2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double m = fma(5.0, pm[k][c], Pv[c] - 6.0 * Pe[c]) + 2.0 * (pm[INC[k][0]][c] + pm[INC[k][1]][c] + pm[INC[k][2]][c]);
+            T m = fma(T(5), pm[k][c], Pv[c] - T(6) * Pe[c]) + T(2) * (pm[INC[k][0]][c] + pm[INC[k][1]][c] + pm[INC[k][2]][c]);
             f[c] = fma(mc, m, f[c]);
         }
         emit(k, f[0], f[1], f[2]);
@@ -246,21 +184,21 @@ __device__ __forceinline__ void element_apply_emit(const double (&pm)[10][3], co
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
         const int k = EV[m][0], j = EV[m][1], o = EV[m][2];
-        const double* gj = G.g[j];
-        const double* gk = G.g[k];
-        double A[6], B[6];
+        const T* gj = G.g[j];
+        const T* gk = G.g[k];
+        T A[6], B[6];
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            A[q] = 4.0 * (sg[k][q] + S[q]);
-            B[q] = 4.0 * (sg[j][q] + S[q]);
+            A[q] = T(4) * (sg[k][q] + S[q]);
+            B[q] = T(4) * (sg[j][q] + S[q]);
         }
-        double f[3];
+        T f[3];
         f[0] = A[0] * gj[0] + A[3] * gj[1] + A[4] * gj[2] + B[0] * gk[0] + B[3] * gk[1] + B[4] * gk[2];
         f[1] = A[3] * gj[0] + A[1] * gj[1] + A[5] * gj[2] + B[3] * gk[0] + B[1] * gk[1] + B[5] * gk[2];
         f[2] = A[4] * gj[0] + A[5] * gj[1] + A[2] * gj[2] + B[4] * gk[0] + B[5] * gk[1] + B[2] * gk[2];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double mm = fma(16.0, Pe[c], -6.0 * Pv[c]) + 2.0 * (pm[k][c] + pm[j][c]) + 16.0 * pm[4 + m][c] - 8.0 * pm[o][c];
+            T mm = fma(T(16), Pe[c], -T(6) * Pv[c]) + T(2) * (pm[k][c] + pm[j][c]) + T(16) * pm[4 + m][c] - T(8) * pm[o][c];
             f[c] = fma(mc, mm, f[c]);
         }
         emit(4 + m, f[0], f[1], f[2]);
@@ -272,13 +210,16 @@ __device__ __forceinline__ void element_apply_emit(const double (&pm)[10][3], co
 // ---------------------------------------------------------------------------
 enum { MODE_APPLY = 0, MODE_PCG = 1, MODE_RHS = 2 };
 
+// Operands of the element kernels.  APPLY and RHS read FP64 vectors; PCG reads
+// z and p_prev in the storage type S of its solve and writes p_cur in S and the
+// slots in the compute type T.
 struct EbeArgs {
     DevPatches P;
-    const double* in0;   // APPLY: p; PCG: z; RHS: u
-    const double* in1;   // PCG: p_prev; RHS: v
+    const void* in0;     // APPLY: p; PCG: z; RHS: u
+    const void* in1;     // PCG: p_prev; RHS: v
     const double* in2;   // RHS: a
-    double* p_cur;       // PCG
-    double* qbuf;
+    void* p_cur;         // PCG
+    void* qbuf;
     double cm, ck;
     double c1, c2;       // RHS: w1 = a + c1 v - g, w2 = c2 v - u
     double g0, g1, g2;
@@ -292,14 +233,14 @@ __device__ __forceinline__ bool check_due(const DevScalars* sc) {
     return (sc->done == DONE_CONVERGED || sc->done == DONE_MAXITER) && !sc->checked;
 }
 
-// One patch on one workgroup of kEbeWaves wavefronts (one element per lane).
-// The waves share the gather of the patch's nodes into LDS; wave w adds its
-// elements' results into its own LDS accumulator (a single wave issues its
-// LDS atomics in program order), and the kEbeWaves accumulators are summed in
-// a fixed order: results are bitwise reproducible.  Returns this thread's
-// share of (p, A p) (PCG).
-template <int MODE>
-__device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double beta, double* lds) {
+// One patch on one workgroup of kEbeWaves wavefronts (one element per thread),
+// compute type T, storage type S of the PCG vectors.  The waves share the
+// gather of the patch's nodes into LDS; wave w adds its elements' results into
+// its own LDS accumulator (a single wave issues its LDS atomics in program
+// order), and the kEbeWaves accumulators are summed in a fixed order: results
+// are bitwise reproducible.  Returns this thread's share of (p, A p) (PCG).
+template <int MODE, class T, class S>
+__device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double beta_d, double* lds) {
     const DevPatches& P = A.P;
     constexpr int NT = 64 * kEbeWaves;
     const int tid = threadIdx.x, wave = tid >> 6;
@@ -307,10 +248,16 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     const int nv = P.nv[patch];
     const int e0 = P.el_ptr[patch], ne = P.el_ptr[patch + 1] - e0;
     const int stride = 3 * P.max_pn;
-    double* lm = lds;                                           // [max_pn][3] mass (or shared) operand
-    double* lk = lm + stride;                                   // [max_pn][3] stiffness operand (RHS)
-    double* la = lk + (MODE == MODE_RHS ? stride : 0);          // kEbeWaves x [max_pn][3] accumulators
-    double* lx = la + kEbeWaves * stride;                       // [max_nv][3] vertex coordinates
+    const T beta = (T)beta_d;
+    // The per-wave accumulators are FP64 in every variant: LDS FP32 atomic adds
+    // were measured to stall the LDS queue (about 8x the issue wait of the FP64
+    // ones), and FP64 accumulation is at least as accurate.
+    double* la = lds;                                      // kEbeWaves x [max_pn][3] accumulators
+    T* lm = reinterpret_cast<T*>(la + kEbeWaves * stride); // [max_pn][3] mass (or shared) operand
+    T* lk = lm + stride;                                   // [max_pn][3] stiffness operand (RHS)
+    T* lx = lk + (MODE == MODE_RHS ? stride : 0);          // [max_nv][3] vertex coordinates
+    const S* in0 = static_cast<const S*>(A.in0);
+    const S* in1 = static_cast<const S*>(A.in1);
 
     // Gather: all loads of a group of GU x NT node entries are issued before any is consumed.
     constexpr int GU = 2;
@@ -321,7 +268,7 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
             const int j = jb + tid + NT * u;
             ent[u] = j < npn ? P.nodes[pn0 + j] : 0u;
         }
-        double v[GU][3], w[GU][3], xc[GU][3];
+        T v[GU][3], w[GU][3], xc[GU][3];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int j = jb + tid + NT * u;
@@ -329,19 +276,20 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
             const bool ok = j < npn;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                v[u][c] = ok ? A.in0[3 * g + c] : 0.0;
-                w[u][c] = (ok && (MODE == MODE_RHS || (MODE == MODE_PCG && beta != 0.0))) ? A.in1[3 * g + c] : 0.0;
-                xc[u][c] = (ok && j < nv) ? P.coords[3 * g + c] : 0.0;
+                v[u][c] = ok ? from_storage<T>(in0[3 * g + c]) : T(0);
+                w[u][c] = (ok && (MODE == MODE_RHS || (MODE == MODE_PCG && beta_d != 0.0)))
+                              ? from_storage<T>(in1[3 * g + c]) : T(0);
+                xc[u][c] = (ok && j < nv) ? (T)P.coords[3 * g + c] : T(0);
             }
         }
-        double a3[GU][3];
+        T a3[GU][3];
         if (MODE == MODE_RHS) {
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
                 const int j = jb + tid + NT * u;
                 const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) a3[u][c] = j < npn ? A.in2[3 * g + c] : 0.0;
+                for (int c = 0; c < 3; ++c) a3[u][c] = j < npn ? (T)A.in2[3 * g + c] : T(0);
             }
         }
 #pragma unroll
@@ -349,29 +297,33 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
             const int j = jb + tid + NT * u;
             if (j >= npn) continue;
             const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
-            double v0 = v[u][0], v1 = v[u][1], v2 = v[u][2];
+            T v0 = v[u][0], v1 = v[u][1], v2 = v[u][2];
             if (MODE == MODE_APPLY) {
                 if (A.mask_in) {
                     uint8_t fm = P.fixmask[g];
-                    if (fm & 1) v0 = 0.0;
-                    if (fm & 2) v1 = 0.0;
-                    if (fm & 4) v2 = 0.0;
+                    if (fm & 1) v0 = T(0);
+                    if (fm & 2) v1 = T(0);
+                    if (fm & 4) v2 = T(0);
                 }
             } else if (MODE == MODE_PCG) {
                 v0 = fma(beta, w[u][0], v0);
                 v1 = fma(beta, w[u][1], v1);
                 v2 = fma(beta, w[u][2], v2);
+                // the matvec uses p as stored, so that q = A p holds for the stored p
+                const S s0 = to_storage<S>(v0), s1 = to_storage<S>(v1), s2 = to_storage<S>(v2);
+                v0 = from_storage<T>(s0); v1 = from_storage<T>(s1); v2 = from_storage<T>(s2);
                 if (ent[u] & kOwnerBit) {
-                    A.p_cur[3 * g] = v0; A.p_cur[3 * g + 1] = v1; A.p_cur[3 * g + 2] = v2;
+                    S* pc = static_cast<S*>(A.p_cur);
+                    pc[3 * g] = s0; pc[3 * g + 1] = s1; pc[3 * g + 2] = s2;
                 }
             } else {  // RHS: v = u, w = v (velocity), a3 = a
-                const double u0 = v0, u1 = v1, u2 = v2;
-                v0 = fma(A.c1, w[u][0], a3[u][0]) - A.g0;
-                v1 = fma(A.c1, w[u][1], a3[u][1]) - A.g1;
-                v2 = fma(A.c1, w[u][2], a3[u][2]) - A.g2;
-                lk[3 * j] = fma(A.c2, w[u][0], -u0);
-                lk[3 * j + 1] = fma(A.c2, w[u][1], -u1);
-                lk[3 * j + 2] = fma(A.c2, w[u][2], -u2);
+                const T u0 = v0, u1 = v1, u2 = v2;
+                v0 = fma((T)A.c1, w[u][0], a3[u][0]) - (T)A.g0;
+                v1 = fma((T)A.c1, w[u][1], a3[u][1]) - (T)A.g1;
+                v2 = fma((T)A.c1, w[u][2], a3[u][2]) - (T)A.g2;
+                lk[3 * j] = fma((T)A.c2, w[u][0], -u0);
+                lk[3 * j + 1] = fma((T)A.c2, w[u][1], -u1);
+                lk[3 * j + 2] = fma((T)A.c2, w[u][2], -u2);
             }
             lm[3 * j] = v0; lm[3 * j + 1] = v1; lm[3 * j + 2] = v2;
 #pragma unroll
@@ -389,25 +341,26 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     if (tid < ne) {
         double* acc = la + wave * stride;
         const ElemRec rec = P.elems[e0 + tid];
-        Geo G;
-        tet_geo(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
+        GeoT<T> G;
+        tet_geo<T>(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
         const double* mp = P.mat + 3 * rec.mat;
-        double w = G.V * (1.0 / 20.0) * A.ck;
-        double lamV = mp[0] * w, muV = mp[1] * w;
-        double mc = A.cm * mp[2] * G.V * (1.0 / 420.0);
-        double pm[10][3], pk[10][3];
+        const T w = G.V * T(1.0 / 20.0) * (T)A.ck;
+        const T lamV = (T)mp[0] * w, muV = (T)mp[1] * w;
+        const T mc = (T)(A.cm * mp[2]) * G.V * T(1.0 / 420.0);
+        T pm[10][3], pk[10][3];
 #pragma unroll
         for (int i = 0; i < 10; ++i) {
             const int l = rec.lid[i];
 #pragma unroll
             for (int c = 0; c < 3; ++c) pm[i][c] = lm[3 * l + c];
         }
-        auto emit = [&](int i, double f0, double f1, double f2) {
+        T papT = T(0);
+        auto emit = [&](int i, T f0, T f1, T f2) {
             const int l = rec.lid[i];
-            lds_add(acc + 3 * l, f0);
-            lds_add(acc + 3 * l + 1, f1);
-            lds_add(acc + 3 * l + 2, f2);
-            if (MODE == MODE_PCG) pap = fma(pm[i][0], f0, fma(pm[i][1], f1, fma(pm[i][2], f2, pap)));
+            lds_add(acc + 3 * l, (double)f0);
+            lds_add(acc + 3 * l + 1, (double)f1);
+            lds_add(acc + 3 * l + 2, (double)f2);
+            if (MODE == MODE_PCG) papT = fma(pm[i][0], f0, fma(pm[i][1], f1, fma(pm[i][2], f2, papT)));
         };
         if (MODE == MODE_RHS) {
 #pragma unroll
@@ -416,12 +369,14 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
 #pragma unroll
                 for (int c = 0; c < 3; ++c) pk[i][c] = lk[3 * l + c];
             }
-            element_apply_emit(pm, pk, G, lamV, muV, mc, emit);
+            element_apply_emit<T>(pm, pk, G, lamV, muV, mc, emit);
         } else {
-            element_apply_emit(pm, pm, G, lamV, muV, mc, emit);
+            element_apply_emit<T>(pm, pm, G, lamV, muV, mc, emit);
         }
+        pap = (double)papT;
     }
     __syncthreads();
+    T* qb = static_cast<T*>(A.qbuf);
     for (int jb = 0; jb < npn; jb += NT * GU) {
         int sl[GU];
 #pragma unroll
@@ -440,8 +395,8 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
                 q1 += la[q * stride + 3 * j + 1];
                 q2 += la[q * stride + 3 * j + 2];
             }
-            double* qo = A.qbuf + 3 * (int64_t)sl[u];
-            qo[0] = q0; qo[1] = q1; qo[2] = q2;
+            T* qo = qb + 3 * (int64_t)sl[u];
+            qo[0] = (T)q0; qo[1] = (T)q1; qo[2] = (T)q2;
         }
     }
     __syncthreads();   // LDS is reused by the next patch of a persistent workgroup
@@ -453,9 +408,10 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
     if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
     extern __shared__ double lds[];
     const int patch = xcd_remap(blockIdx.x, gridDim.x);
-    ebe_patch<MODE>(A, patch, 0.0, lds);
+    ebe_patch<MODE, double, double>(A, patch, 0.0, lds);
 }
 
+// FP64 sizing; it also covers the FP32 operands of the low-precision variants.
 size_t ebe_lds_bytes(const DevPatches& P, int mode) {
     return sizeof(double) * (size_t)(3 * P.max_pn * ((mode == MODE_RHS ? 2 : 1) + kEbeWaves) + 3 * P.max_nv);
 }
@@ -468,12 +424,14 @@ size_t ebe_lds_bytes(const DevPatches& P, int mode) {
 // next kernel sums all partials in the same fixed order (the kernel boundary
 // makes them visible), so alpha, beta and the stop test are bitwise identical
 // in every workgroup.  Workgroup 0 records the scalars for later kernels and
-// the host.  Partial slots are double-buffered by iteration parity.
+// the host.  Partial slots (kResArrays arrays of g_res values: (z,r), (r,r),
+// (b,b), (z,r_prev)) are double-buffered by trip parity.
 
 struct PcgEbeArgs {
     EbeArgs E;
     DevScalars* sc;
-    const double* res_part;   // [3][g_res] (z,r), (r,r), (b,b) of the residual entering trip j
+    const DevScalars* outer;  // inner solves: stop as soon as the outer solve has stopped
+    const double* res_part;   // slot read by trip j
     int g_res;
     double* pap_part;         // [gridDim.x] (p, A p) partials written here
     int j;                    // trip index within the solve (0-based)
@@ -481,25 +439,31 @@ struct PcgEbeArgs {
     double tol;
 };
 
-// Trip j of Algorithm 1, matvec part: stop test on the incoming residual,
-// beta = rho_j / rho_{j-1} (0 on the first trip of a cycle), p = z + beta p,
-// q = A p (patch slots) and the partials of (p, A p).  Persistent grid: each
-// workgroup walks a contiguous (per XCD) range of patches.
 __device__ __forceinline__ double block_bcast_sum(double v);
 
+// Trip j of Algorithm 1, matvec part: stop test on the incoming residual,
+// beta = rho_j / rho_{j-1} (0 on the first trip of a cycle; with FLEX the
+// Polak-Ribiere form (rho_j - (z_j, r_{j-1})) / rho_{j-1} of flexible CG),
+// p = z + beta p, q = A p (patch slots) and the partials of (p, A p).
+// Persistent grid: each workgroup walks a contiguous (per XCD) range of patches.
+template <class T, class S, bool FLEX>
 __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe_pcg(PcgEbeArgs A) {
     DevScalars* sc = A.sc;
     if (sc->done) return;
+    if (A.outer && A.outer->done) return;
     extern __shared__ double lds[];
     constexpr int NT = 64 * kEbeWaves;
     const int tid = threadIdx.x;
     const int j = A.j;
-    double zr = lane_partials<kMaxResGrid / NT>(A.res_part, A.g_res, tid, NT);
-    double rr = lane_partials<kMaxResGrid / NT>(A.res_part + A.g_res, A.g_res, tid, NT);
-    double bb = j == 0 ? lane_partials<kMaxResGrid / NT>(A.res_part + 2 * A.g_res, A.g_res, tid, NT) : 0.0;
+    const int g = A.g_res;
+    double zr = lane_partials<kMaxResGrid / NT>(A.res_part, g, tid, NT);
+    double rr = lane_partials<kMaxResGrid / NT>(A.res_part + g, g, tid, NT);
+    double bb = j == 0 ? lane_partials<kMaxResGrid / NT>(A.res_part + 2 * g, g, tid, NT) : 0.0;
+    double zp = (FLEX && j != sc->cycle_start) ? lane_partials<kMaxResGrid / NT>(A.res_part + 3 * g, g, tid, NT) : 0.0;
     zr = block_bcast_sum(zr);
     rr = block_bcast_sum(rr);
     bb = block_bcast_sum(bb);
+    if (FLEX) zp = block_bcast_sum(zp);
     const double bnorm = (j == 0) ? sqrt(bb) : sc->bnorm;
     const double res = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
     int stop = DONE_RUNNING;
@@ -509,7 +473,7 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe_pcg(PcgEbeArgs A) {
     else if (j >= A.max_iter) stop = DONE_MAXITER;
     double beta = 0.0;
     if (stop == DONE_RUNNING && j != sc->cycle_start) {
-        beta = zr / sc->rho[(j - 1) & 1];
+        beta = (zr - zp) / sc->rho[(j - 1) & 1];
         if (!isfinite(beta)) stop = DONE_NONFINITE;
     }
     if (blockIdx.x == 0 && tid == 0) {
@@ -532,7 +496,8 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe_pcg(PcgEbeArgs A) {
     const int xcd = blockIdx.x & 7, k0 = blockIdx.x >> 3, per_xcd_wg = nb >> 3;
     const int chunk = A.E.P.n_patches_pad >> 3;
     double pap = 0.0;
-    for (int k = k0; k < chunk; k += per_xcd_wg) pap += ebe_patch<MODE_PCG>(A.E, xcd * chunk + k, beta, lds);
+    for (int k = k0; k < chunk; k += per_xcd_wg)
+        pap += ebe_patch<MODE_PCG, T, S>(A.E, xcd * chunk + k, beta, lds);
     pap = block_bcast_sum(pap);
     if (tid == 0) A.pap_part[blockIdx.x] = pap;
 }
@@ -557,12 +522,12 @@ bool ebe_set_lds_limit(const DevPatches& P) {
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return false;
     if (need > (size_t)maxlds) return false;
     const int v = (int)need;
-    bool ok = hipFuncSetAttribute((const void*)k_ebe<MODE_APPLY>, hipFuncAttributeMaxDynamicSharedMemorySize, v) ==
-              hipSuccess;
-    ok = ok && hipFuncSetAttribute((const void*)k_ebe<MODE_RHS>, hipFuncAttributeMaxDynamicSharedMemorySize, v) ==
-                   hipSuccess;
-    ok = ok && hipFuncSetAttribute((const void*)k_ebe_pcg, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess;
-    return ok;
+    const void* fns[] = {(const void*)k_ebe<MODE_APPLY>, (const void*)k_ebe<MODE_RHS>,
+                         (const void*)k_ebe_pcg<double, double, false>, (const void*)k_ebe_pcg<double, double, true>,
+                         (const void*)k_ebe_pcg<float, float, false>, (const void*)k_ebe_pcg<float, bf16_t, false>};
+    for (const void* f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess) return false;
+    return true;
 }
 
 void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
@@ -579,14 +544,22 @@ int pcg_ebe_grid(const DevPatches& P) {
     return g;   // n_patches_pad and kMaxPcgGrid are multiples of 8, so is g
 }
 
-void launch_ebe_pcg(hipStream_t s, const DevPatches& P, const double* z, const double* p_prev, double* p_cur,
-                    double cm, double ck, double* qbuf, DevScalars* sc, const double* res_part, int g_res,
-                    double* pap_part, int j, int max_iter, double tol) {
+void launch_ebe_pcg(hipStream_t s, const PcgLaunch& L) {
     PcgEbeArgs A{};
-    A.E.P = P; A.E.in0 = z; A.E.in1 = p_prev; A.E.p_cur = p_cur; A.E.qbuf = qbuf; A.E.cm = cm; A.E.ck = ck;
-    A.sc = sc; A.res_part = res_part; A.g_res = g_res; A.pap_part = pap_part; A.j = j; A.max_iter = max_iter;
-    A.tol = tol;
-    hipLaunchKernelGGL(k_ebe_pcg, dim3(pcg_ebe_grid(P)), dim3(64 * kEbeWaves), ebe_lds_bytes(P, MODE_PCG), s, A);
+    A.E.P = *L.P; A.E.in0 = L.z; A.E.in1 = L.p_prev; A.E.p_cur = L.p_cur; A.E.qbuf = L.qbuf;
+    A.E.cm = L.cm; A.E.ck = L.ck;
+    A.sc = L.sc; A.outer = L.outer; A.res_part = L.res_part; A.g_res = L.g_res; A.pap_part = L.pap_part;
+    A.j = L.j; A.max_iter = L.max_iter; A.tol = L.tol;
+    const size_t lds = ebe_lds_bytes(*L.P, MODE_PCG);   // FP64 sizing also covers FP32 operands
+    const dim3 grid(pcg_ebe_grid(*L.P)), block(64 * kEbeWaves);
+    switch (L.prec) {
+        case PREC_FP64:
+            if (L.flexible) hipLaunchKernelGGL((k_ebe_pcg<double, double, true>), grid, block, lds, s, A);
+            else hipLaunchKernelGGL((k_ebe_pcg<double, double, false>), grid, block, lds, s, A);
+            break;
+        case PREC_FP32: hipLaunchKernelGGL((k_ebe_pcg<float, float, false>), grid, block, lds, s, A); break;
+        default: hipLaunchKernelGGL((k_ebe_pcg<float, bf16_t, false>), grid, block, lds, s, A); break;
+    }
 }
 
 void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const double* v, const double* a,
@@ -668,10 +641,10 @@ void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, d
 // ---------------------------------------------------------------------------
 // node-wise kernels
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void gather_q(const DevNodes& N, const double* qbuf, int64_t n, double& q0, double& q1,
-                                         double& q2) {
+template <class T>
+__device__ __forceinline__ void gather_q(const DevNodes& N, const T* qbuf, int64_t n, T& q0, T& q1, T& q2) {
     const int k0 = N.slot_ptr[n], k1 = N.slot_ptr[n + 1];
-    const double* q = qbuf + 3 * (int64_t)k0;
+    const T* q = qbuf + 3 * (int64_t)k0;
     q0 = q[0]; q1 = q[1]; q2 = q[2];
     for (int k = 1; k < k1 - k0; ++k) {
         q0 += q[3 * k]; q1 += q[3 * k + 1]; q2 += q[3 * k + 2];
@@ -726,8 +699,8 @@ void launch_diag_finalize(hipStream_t s, const DevNodes& N, const double* qbuf6,
     hipLaunchKernelGGL(k_diag_finalize, dim3(nb), dim3(256), 0, s, N, qbuf6, binv6);
 }
 
-__device__ __forceinline__ void apply_binv(const double* B, double r0, double r1, double r2, double& z0, double& z1,
-                                           double& z2) {
+template <class T>
+__device__ __forceinline__ void apply_binv(const T* B, T r0, T r1, T r2, T& z0, T& z1, T& z2) {
     z0 = B[0] * r0 + B[3] * r1 + B[4] * r2;
     z1 = B[3] * r0 + B[1] * r1 + B[5] * r2;
     z2 = B[4] * r0 + B[5] * r1 + B[2] * r2;
@@ -788,6 +761,7 @@ __global__ __launch_bounds__(256) void k_residual(DevNodes N, const double* qbuf
         sc->restarts = 0;
         sc->checked = 0;
         sc->cycle_start = 0;
+        sc->inner_iters = 0;
         sc->res_true = 0.0;
     }
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
@@ -857,24 +831,29 @@ void launch_check_finalize(hipStream_t s, DevScalars* sc, const double* res_part
 
 // Trip j, update part: alpha = rho_j / (p, A p) from the matvec partials,
 // r -= alpha q, x += alpha p, z = B^{-1} r, and partials of (z, r), (r, r)
-// for trip j + 1.  Persistent grid-stride over nodes.
-__global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qbuf, const double* p,
-                                                    const double* binv6, double* x, double* r, double* z,
-                                                    DevScalars* sc, const double* pap_part, int g_pap,
-                                                    double* res_part, int j) {
+// for trip j + 1.  Compute type T, storage type S of p and z.  Persistent
+// grid-stride over nodes; two nodes per thread per trip with all loads first.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, const S* p, const T* binv6, T* x, T* r,
+                                                    S* z, DevScalars* sc, const DevScalars* outer,
+                                                    const double* pap_part, int g_pap, double* res_part, int j,
+                                                    int32_t* inner_count) {
     if (sc->done) return;
+    if (outer && outer->done) return;
     double pap = lane_partials<kMaxPcgGrid / 256>(pap_part, g_pap, threadIdx.x, 256);
     pap = block_bcast_sum(pap);
-    const double alpha = sc->rho[j & 1] / pap;
-    if (!isfinite(alpha)) {
+    const double alpha_d = sc->rho[j & 1] / pap;
+    if (!isfinite(alpha_d)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = DONE_NONFINITE;
         return;
     }
+    if (inner_count && blockIdx.x == 0 && threadIdx.x == 0) *inner_count += 1;
+    const T alpha = (T)alpha_d;
     double v0 = 0.0, v1 = 0.0;
     constexpr int U = 2;   // nodes per thread per trip, loads of all of them issued first
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n0 < N.n; n0 += U * stride) {
-        double q[U][3], rv[U][3], xv[U][3], pv[U][3], B[U][6];
+        T q[U][3], rv[U][3], xv[U][3], pv[U][3], B[U][6];
         uint8_t fm[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -884,32 +863,34 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qb
             fm[u] = ok ? N.fixmask[n] : 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                rv[u][c] = ok ? r[3 * n + c] : 0.0;
-                xv[u][c] = ok ? x[3 * n + c] : 0.0;
-                pv[u][c] = ok ? p[3 * n + c] : 0.0;
+                rv[u][c] = ok ? r[3 * n + c] : T(0);
+                xv[u][c] = ok ? x[3 * n + c] : T(0);
+                pv[u][c] = ok ? from_storage<T>(p[3 * n + c]) : T(0);
             }
 #pragma unroll
-            for (int t = 0; t < 6; ++t) B[u][t] = ok ? binv6[6 * n + t] : 0.0;
+            for (int t = 0; t < 6; ++t) B[u][t] = ok ? binv6[6 * n + t] : T(0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t n = n0 + u * stride;
             if (n >= N.n) continue;
-            if (fm[u] & 1) q[u][0] = 0.0;
-            if (fm[u] & 2) q[u][1] = 0.0;
-            if (fm[u] & 4) q[u][2] = 0.0;
-            const double r0 = fma(-alpha, q[u][0], rv[u][0]);
-            const double r1 = fma(-alpha, q[u][1], rv[u][1]);
-            const double r2 = fma(-alpha, q[u][2], rv[u][2]);
+            if (fm[u] & 1) q[u][0] = T(0);
+            if (fm[u] & 2) q[u][1] = T(0);
+            if (fm[u] & 4) q[u][2] = T(0);
+            const T r0 = fma(-alpha, q[u][0], rv[u][0]);
+            const T r1 = fma(-alpha, q[u][1], rv[u][1]);
+            const T r2 = fma(-alpha, q[u][2], rv[u][2]);
             x[3 * n] = fma(alpha, pv[u][0], xv[u][0]);
             x[3 * n + 1] = fma(alpha, pv[u][1], xv[u][1]);
             x[3 * n + 2] = fma(alpha, pv[u][2], xv[u][2]);
-            double z0, z1, z2;
+            T z0, z1, z2;
             apply_binv(B[u], r0, r1, r2, z0, z1, z2);
             r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
-            z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
-            v0 += z0 * r0 + z1 * r1 + z2 * r2;
-            v1 += r0 * r0 + r1 * r1 + r2 * r2;
+            const S zs0 = to_storage<S>(z0), zs1 = to_storage<S>(z1), zs2 = to_storage<S>(z2);
+            z[3 * n] = zs0; z[3 * n + 1] = zs1; z[3 * n + 2] = zs2;
+            // dots in FP64 with the stored z (what the next matvec reads)
+            v0 += (double)from_storage<T>(zs0) * r0 + (double)from_storage<T>(zs1) * r1 + (double)from_storage<T>(zs2) * r2;
+            v1 += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
         }
     }
     v0 = block_bcast_sum(v0);
@@ -920,11 +901,188 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const double* qb
     }
 }
 
-void launch_pcg_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, const double* binv6,
-                       double* x, double* r, double* z, DevScalars* sc, const double* pap_part, int g_pap,
-                       double* res_part, int j) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(res_grid(N.n)), dim3(256), 0, s, N, qbuf, p, binv6, x, r, z, sc, pap_part,
-                       g_pap, res_part, j);
+void launch_pcg_update(hipStream_t s, const UpdLaunch& L) {
+    const dim3 grid(res_grid(L.N->n)), block(256);
+    switch (L.prec) {
+        case PREC_FP64:
+            hipLaunchKernelGGL((k_pcg_update<double, double>), grid, block, 0, s, *L.N, (const double*)L.qbuf,
+                               (const double*)L.p, (const double*)L.binv, (double*)L.x, (double*)L.r, (double*)L.z,
+                               L.sc, L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count);
+            break;
+        case PREC_FP32:
+            hipLaunchKernelGGL((k_pcg_update<float, float>), grid, block, 0, s, *L.N, (const float*)L.qbuf,
+                               (const float*)L.p, (const float*)L.binv, (float*)L.x, (float*)L.r, (float*)L.z, L.sc,
+                               L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count);
+            break;
+        default:
+            hipLaunchKernelGGL((k_pcg_update<float, bf16_t>), grid, block, 0, s, *L.N, (const float*)L.qbuf,
+                               (const bf16_t*)L.p, (const float*)L.binv, (float*)L.x, (float*)L.r, (bf16_t*)L.z,
+                               L.sc, L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count);
+            break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: flexible FP64 outer PCG, inner FP32 / BF16-stored PCG
+// ---------------------------------------------------------------------------
+// Start of the inner solve for outer trip j: outer stop test on the outer
+// residual partials of slot j (the remaining kernels of the trip return at
+// once when it fires), then r_in = float(r), e = 0, z = B^{-1} r_in and the
+// inner partials (z,r), (r,r), (r,r) into the inner slot 0.  Resets the inner
+// scalars.
+template <class T, class S>
+__global__ __launch_bounds__(256) void k_inner_init(DevNodes N, const double* r64, const T* binv6, T* r, T* e, S* z,
+                                                    DevScalars* outer, const double* outer_part, int g_out, int j,
+                                                    int max_iter, double tol, DevScalars* sc_in, double* in_part) {
+    if (outer->done) return;
+    const int g = g_out;
+    double rr = lane_partials<kMaxResGrid / 256>(outer_part + g, g, threadIdx.x, 256);
+    double bb = j == 0 ? lane_partials<kMaxResGrid / 256>(outer_part + 2 * g, g, threadIdx.x, 256) : 0.0;
+    rr = block_bcast_sum(rr);
+    bb = block_bcast_sum(bb);
+    const double bnorm = (j == 0) ? sqrt(bb) : outer->bnorm;
+    const double res = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
+    int stop = DONE_RUNNING;
+    if (bnorm == 0.0) stop = DONE_ZERO_RHS;
+    else if (!isfinite(res)) stop = DONE_NONFINITE;
+    else if (res < tol) stop = DONE_CONVERGED;
+    else if (j >= max_iter) stop = DONE_MAXITER;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (stop != DONE_RUNNING) {
+            outer->done = stop;
+            outer->iters = j;
+            outer->rr = rr;
+            if (j == 0) {
+                outer->bnorm = bnorm;
+                outer->res0 = res;
+            }
+        }
+        sc_in->done = DONE_RUNNING;
+        sc_in->cycle_start = 0;
+        sc_in->checked = 0;
+    }
+    if (stop != DONE_RUNNING) return;
+    double v0 = 0.0, v1 = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
+        const uint8_t fm = N.fixmask[n];
+        T r0 = (fm & 1) ? T(0) : (T)r64[3 * n];
+        T r1 = (fm & 2) ? T(0) : (T)r64[3 * n + 1];
+        T r2 = (fm & 4) ? T(0) : (T)r64[3 * n + 2];
+        T B[6];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) B[t] = binv6[6 * n + t];
+        T z0, z1, z2;
+        apply_binv(B, r0, r1, r2, z0, z1, z2);
+        r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
+        e[3 * n] = T(0); e[3 * n + 1] = T(0); e[3 * n + 2] = T(0);
+        const S zs0 = to_storage<S>(z0), zs1 = to_storage<S>(z1), zs2 = to_storage<S>(z2);
+        z[3 * n] = zs0; z[3 * n + 1] = zs1; z[3 * n + 2] = zs2;
+        v0 += (double)from_storage<T>(zs0) * r0 + (double)from_storage<T>(zs1) * r1 + (double)from_storage<T>(zs2) * r2;
+        v1 += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
+    }
+    v0 = block_bcast_sum(v0);
+    v1 = block_bcast_sum(v1);
+    if (threadIdx.x == 0) {
+        in_part[blockIdx.x] = v0;
+        in_part[gridDim.x + blockIdx.x] = v1;
+        in_part[2 * gridDim.x + blockIdx.x] = v1;   // the inner right-hand side is r itself
+    }
+}
+
+// Outer trip j, preconditioned residual: z = e (the inner solution, in FP64)
+// and the partials (z, r), (r, r), (z, r_prev) of slot j for the flexible
+// matvec kernel.
+template <class T>
+__global__ __launch_bounds__(256) void k_outer_z(DevNodes N, const T* e, const double* r, const double* r_prev,
+                                                 double* z, const DevScalars* outer, double* part, int j) {
+    if (outer->done) return;
+    const bool prev = j != outer->cycle_start;
+    double v0 = 0.0, v1 = 0.0, v3 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * N.n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double zi = (double)e[i];
+        const double ri = r[i];
+        z[i] = zi;
+        v0 += zi * ri;
+        v1 += ri * ri;
+        if (prev) v3 += zi * r_prev[i];
+    }
+    v0 = block_bcast_sum(v0);
+    v1 = block_bcast_sum(v1);
+    v3 = block_bcast_sum(v3);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v0;
+        part[gridDim.x + blockIdx.x] = v1;
+        part[3 * gridDim.x + blockIdx.x] = v3;
+    }
+}
+
+// Outer trip j, update: alpha = rho_j / (p, A p); r_prev = r; r -= alpha q
+// (fixed rows masked); x += alpha p; partials (r, r) into slot j + 1.
+__global__ __launch_bounds__(256) void k_outer_update(DevNodes N, const double* qbuf, const double* p, double* x,
+                                                      double* r, double* r_prev, DevScalars* sc,
+                                                      const double* pap_part, int g_pap, double* part, int j) {
+    if (sc->done) return;
+    double pap = lane_partials<kMaxPcgGrid / 256>(pap_part, g_pap, threadIdx.x, 256);
+    pap = block_bcast_sum(pap);
+    const double alpha = sc->rho[j & 1] / pap;
+    if (!isfinite(alpha)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = DONE_NONFINITE;
+        return;
+    }
+    double v1 = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
+        double q0, q1, q2;
+        gather_q(N, qbuf, n, q0, q1, q2);
+        const uint8_t fm = N.fixmask[n];
+        if (fm & 1) q0 = 0.0;
+        if (fm & 2) q1 = 0.0;
+        if (fm & 4) q2 = 0.0;
+        const double qq[3] = {q0, q1, q2};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double ro = r[3 * n + c];
+            const double rn = fma(-alpha, qq[c], ro);
+            r_prev[3 * n + c] = ro;
+            r[3 * n + c] = rn;
+            x[3 * n + c] = fma(alpha, p[3 * n + c], x[3 * n + c]);
+            v1 += rn * rn;
+        }
+    }
+    v1 = block_bcast_sum(v1);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = v1;
+}
+
+__global__ void k_to_f32(int64_t n, const double* in, float* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
+void launch_inner_init(hipStream_t s, int prec, const DevNodes& N, const double* r64, const void* binv, void* r,
+                       void* e, void* z, DevScalars* outer, const double* outer_part, int j, int max_iter, double tol,
+                       DevScalars* sc_in, double* in_part) {
+    const int g = res_grid(N.n);
+    if (prec == PREC_FP32)
+        hipLaunchKernelGGL((k_inner_init<float, float>), dim3(g), dim3(256), 0, s, N, r64, (const float*)binv,
+                           (float*)r, (float*)e, (float*)z, outer, outer_part, g, j, max_iter, tol, sc_in, in_part);
+    else
+        hipLaunchKernelGGL((k_inner_init<float, bf16_t>), dim3(g), dim3(256), 0, s, N, r64, (const float*)binv,
+                           (float*)r, (float*)e, (bf16_t*)z, outer, outer_part, g, j, max_iter, tol, sc_in, in_part);
+}
+
+void launch_outer_z(hipStream_t s, const DevNodes& N, const void* e, const double* r, const double* r_prev, double* z,
+                    const DevScalars* outer, double* part, int j) {
+    hipLaunchKernelGGL((k_outer_z<float>), dim3(res_grid(N.n)), dim3(256), 0, s, N, (const float*)e, r, r_prev, z,
+                       outer, part, j);
+}
+
+void launch_outer_update(hipStream_t s, const DevNodes& N, const double* qbuf, const double* p, double* x, double* r,
+                         double* r_prev, DevScalars* sc, const double* pap_part, int g_pap, double* part, int j) {
+    hipLaunchKernelGGL(k_outer_update, dim3(res_grid(N.n)), dim3(256), 0, s, N, qbuf, p, x, r, r_prev, sc, pap_part,
+                       g_pap, part, j);
+}
+
+void launch_to_f32(hipStream_t s, int64_t n, const double* in, float* out) {
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in, out);
 }
 
 // ---------------------------------------------------------------------------

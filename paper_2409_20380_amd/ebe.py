@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libebe.so")
 OK, NOT_CONVERGED = 0, 1
 E_INVALID_ARG, E_HIP, E_NO_MEMORY, E_BAD_STATE, E_NONFINITE = -1, -2, -3, -4, -5
 PRED_ZERO, PRED_AB4, PRED_SNAPSHOT = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 
 
 class EbeError(RuntimeError):
@@ -30,19 +31,20 @@ class EbeError(RuntimeError):
 
 class Config(C.Structure):
     _fields_ = [("dt", C.c_double), ("rayleigh_alpha", C.c_double), ("rayleigh_beta", C.c_double),
-                ("tol", C.c_double), ("drop_tol", C.c_double), ("max_iter", C.c_int32), ("s", C.c_int32),
-                ("predictor", C.c_int32), ("region_nodes", C.c_int32), ("patch_elems", C.c_int32),
-                ("chunk_iters", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("tol", C.c_double), ("drop_tol", C.c_double), ("inner_tol", C.c_double), ("max_iter", C.c_int32),
+                ("s", C.c_int32), ("predictor", C.c_int32), ("region_nodes", C.c_int32),
+                ("patch_elems", C.c_int32), ("chunk_iters", C.c_int32), ("precision", C.c_int32),
+                ("inner_iters", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("inner_iters", C.c_int32),
                 ("res0", C.c_double), ("res_rec", C.c_double), ("res_true", C.c_double), ("bnorm", C.c_double)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("it", C.c_int32), ("s_eff", C.c_int32), ("iters", C.c_int32), ("restarts", C.c_int32),
-                ("status", C.c_int32), ("pad", C.c_int32), ("res0", C.c_double), ("res_rec", C.c_double),
+                ("status", C.c_int32), ("inner_iters", C.c_int32), ("res0", C.c_double), ("res_rec", C.c_double),
                 ("res_true", C.c_double), ("bnorm", C.c_double)]
 
 
@@ -50,7 +52,7 @@ class StepStats(C.Structure):
 EXPORTS = ("ebe_version", "ebe_create", "ebe_destroy", "ebe_last_error", "ebe_assemble", "ebe_get_regions",
            "ebe_apply", "ebe_apply_mk", "ebe_precond", "ebe_rhs", "ebe_predict", "ebe_refine", "ebe_step",
            "ebe_get_state", "ebe_set_state", "ebe_get_history", "ebe_set_history", "ebe_sync",
-           "ebe_set_kernel_timing", "ebe_kernel_time", "ebe_sizes")
+           "ebe_set_kernel_timing", "ebe_kernel_time", "ebe_sizes", "ebe_get_config")
 
 _lib = None
 vp = C.c_void_p
@@ -90,6 +92,7 @@ def lib():
     L.ebe_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.ebe_kernel_time.argtypes = [vp, i64_p, d_p]
     L.ebe_sizes.argtypes = [vp, i64_p, i64_p, i64_p, i64_p]
+    L.ebe_get_config.argtypes = [vp, C.POINTER(Config)]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
     L.ebe_version.restype = C.c_char_p
@@ -127,12 +130,14 @@ class Solver:
     """One handle of the library: a mesh, its state and its history."""
 
     def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
-                 max_iter=10000, drop_tol=1e-6, region_nodes=512, patch_elems=256, chunk_iters=0, stream=None):
+                 max_iter=10000, drop_tol=1e-6, region_nodes=512, patch_elems=256, chunk_iters=0, precision=PREC_FP64,
+                 inner_iters=0, inner_tol=0.0, stream=None):
         import torch
         L = lib()
         cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol,
                      drop_tol=drop_tol, max_iter=max_iter, s=s, predictor=predictor, region_nodes=region_nodes,
-                     patch_elems=patch_elems, chunk_iters=chunk_iters)
+                     patch_elems=patch_elems, chunk_iters=chunk_iters, precision=precision,
+                     inner_iters=inner_iters, inner_tol=inner_tol)
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -259,6 +264,12 @@ class Solver:
         ms = C.c_double()
         self._check(lib().ebe_kernel_time(self._h, C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+    def effective_config(self):
+        """The configuration the library uses (defaults filled in)."""
+        c = Config()
+        self._check(lib().ebe_get_config(self._h, C.byref(c)))
+        return c
 
     def sizes(self):
         v = [C.c_int64() for _ in range(4)]

@@ -233,6 +233,9 @@ class Workload:
         return mesh, elem_mat, mat, fixed, regions, wave
 
 
-# The small case the oracle finishes in seconds, and the single-GPU headline case.
+# The small case the oracle finishes in seconds, the single-GPU headline case,
+# and the large mesh of the mixed-precision comparison (8.5M nodes, 25.6M dof).
 SMALL = Workload("box8x8x8_p2tet_fp64", cells=(8, 8, 8), nt=100, s=16)
 PLAIN = Workload("box64x64x32_p2tet_fp64", cells=(64, 64, 32), nt=1000, s=32)
+LARGE = Workload("box128x128x64_p2tet", cells=(128, 128, 64), nt=300, s=32)
+WORKLOADS = {"plain": PLAIN, "large": LARGE, "small": SMALL}

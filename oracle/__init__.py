@@ -6,7 +6,8 @@ import this package.  It shares no code with the HIP library
 
 The arithmetic lives in ``oracle.c`` (plain C, FP64, optional OpenMP); this
 module only marshals numpy arrays into it.  See ``oracle.c`` for the
-definitions each function follows.
+definitions each function follows.  ``oracle.mlp`` (NumPy, FP64) holds the
+oracle of the node-wise learned predictor.
 """
 from __future__ import annotations
 

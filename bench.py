@@ -90,7 +90,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.txt"))
     ap.add_argument("--patch-elems", type=int, default=256, help="elements per EBE patch (1..256)")
-    ap.add_argument("--workload", choices=["plain", "large"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "large", "learned"], default="plain")
+    ap.add_argument("--train-seeds", type=int, default=50, help="learned: training trajectories")
+    ap.add_argument("--train-steps", type=int, default=200, help="learned: steps per training trajectory")
+    ap.add_argument("--train-nodes", type=int, default=4096, help="learned: sampled nodes per training step")
+    ap.add_argument("--test-seeds", type=int, default=32, help="learned: test trajectories")
+    ap.add_argument("--test-steps", type=int, default=200, help="learned: steps per test trajectory")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16"], default="fp64",
                     help="fp64: plain PCG; fp32/bf16: flexible FP64 PCG with an inner low-precision PCG")
     ap.add_argument("--inner-iters", type=int, default=0, help="inner PCG trips per outer trip (0: library default)")
@@ -112,6 +117,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "learned":
+        run_learned(args)
+        return
     wl = inputs.WORKLOADS[args.workload]
     prec = {"fp64": ebe.PREC_FP64, "fp32": ebe.PREC_FP32, "bf16": ebe.PREC_BF16}[args.precision]
     nt = args.warmup + args.steps
@@ -203,6 +211,109 @@ def main():
     if not args.no_cpu_baseline and args.workload == "plain":
         log(f"CPU baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(wl_run, mesh, em, mat, fx, regions, wave, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def run_learned(args):
+    """Learned predictor on the 64 x 64 x 32 mesh: train on trajectories the
+    solver generates (own kernels), then compare test trajectories of kind 3
+    (network candidate with fallback) with the plain method (kind 2) and with
+    kind 3 on a zero network (the fallback between AB4 and the snapshot guess
+    alone)."""
+    import numpy as np
+    import torch
+
+    from paper_2409_20380_amd import ebe, inputs, learn
+    base = inputs.PLAIN
+    steps = max(args.train_steps, args.test_steps)
+    wl = inputs.Workload(base.name, cells=base.cells, h=base.h, dt=base.dt, nt=steps, s=base.s, tol=base.tol,
+                         seed=base.seed, region_block=base.region_block)
+    mesh, em, mat, fx, regions, _ = wl.build()
+    aR, bR = wl.rayleigh
+    dof = 3 * mesh.n_nodes
+    sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems)
+    sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
+    nodes = torch.from_numpy(inputs.sample_nodes(3, fx, args.train_nodes)).cuda()
+    seeds = inputs.LEARN_TRAIN_SEEDS[:args.train_seeds]
+    cap = len(seeds) * (args.train_steps - 4) * nodes.numel()
+    t0 = time.time()
+    learn.generate(sol, wl, seeds, args.train_steps, nodes, cap)
+    t_gen = time.time() - t0
+    n_samples = sol.samples().shape[0]
+    log(f"generated {n_samples} samples from {len(seeds)} trajectories in {t_gen:.1f} s")
+    t0 = time.time()
+    losses = learn.train(sol, 1, [(3000, 1e-3), (2000, 3e-4), (1000, 1e-4)], 4096, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    trained, scales = sol.mlp_get()
+
+    def run(kind, seeds_, params, timing=False):
+        sol.set_predictor(kind)
+        if params is not None:
+            sol.mlp_set(params, scales)
+        its, res, picks, el = [], [], [], 0.0
+        for seed in seeds_:
+            w = inputs.base_wave(seed, args.test_steps, wl.dt, *wl.f_band)
+            sol.reset()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for it in range(1, args.test_steps + 1):
+                st = sol.step(base_acc=w[it])
+                if st.status != 0:
+                    raise RuntimeError(f"seed {seed} step {it} did not converge")
+                its.append(st.iters); res.append(st.res_true); picks.append(st.learned)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t
+        picks = np.array(picks)
+        return dict(value=dof * args.test_steps * len(seeds_) / el, ms_per_step=el / (args.test_steps * len(seeds_)) * 1e3,
+                    iters=float(np.mean(its)), max_res=float(np.max(res)),
+                    pick=float((picks == 1).sum() / max(1, (picks >= 0).sum())))
+
+    test = inputs.LEARN_TEST_SEEDS[:args.test_seeds]
+    plain = run(ebe.PRED_SNAPSHOT, test, None)
+    log(f"plain (kind 2): {plain}")
+    sol.set_kernel_timing(args.timing_every)
+    learned = run(ebe.PRED_LEARNED, test, trained)
+    n_timed, ebe_ms = sol.kernel_time()
+    log(f"learned (kind 3): {learned}")
+    zero = run(ebe.PRED_LEARNED, test[:4], np.zeros_like(trained))
+    log(f"selection only (kind 3, zero network, {min(4, len(test))} seeds): {zero}")
+    sol.close()
+    bpe = ebe_pcg_bytes_per_element(mesh.n_nodes, mesh.n_elems)
+    achieved = bpe * mesh.n_elems / (ebe_ms * 1e-3) / 1e9 if ebe_ms > 0 else 0.0
+    out = {
+        "metric": "DOF*steps/s at rel. residual 1e-8",
+        "value": learned["value"],
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.test_steps * len(test),
+        "warmup": 0,
+        "ms_per_step": learned["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (network: bf16 weights, fp32 accumulate)",
+        "data": "synthetic",
+        "config": {"workload": "box64x64x32_learned_predictor", "cells": list(wl.cells), "dof": dof,
+                   "train": f"{len(seeds)} trajectories x {args.train_steps} steps, {args.train_nodes} nodes/step, "
+                            f"{n_samples} samples, 6000 Adam steps (batch 4096)",
+                   "test": f"{len(test)} new waves x {args.test_steps} steps from rest",
+                   "predictor": "kind 3: AB4 + network estimate of the AB4 error vs the AB4 + snapshot guess, "
+                                "smaller initial residual kept"},
+        "plain_value": plain["value"],
+        "speedup_vs_plain": learned["value"] / plain["value"],
+        "cg_iters_per_step": learned["iters"],
+        "plain_cg_iters_per_step": plain["iters"],
+        "learned_pick_fraction": learned["pick"],
+        "selection_only": zero,
+        "max_true_rel_residual": max(learned["max_res"], plain["max_res"]),
+        "train_seconds": {"generate": t_gen, "train": t_train},
+        "final_train_loss": float(np.mean(losses[-50:])),
+        "roofline": {"kernel": "k_ebe<PCG> (fused direction update + EBE matvec + (p,Ap))", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": bpe * mesh.n_elems, "mean_launch_ms": ebe_ms,
+                     "timed_launches": n_timed},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -61,6 +61,15 @@ extern "C" {
 #define EBE_PRED_ZERO 0      /* x-bar = 0 */
 #define EBE_PRED_AB4 1       /* Adams-Bashforth 4-step estimate (Sec. 3.2) */
 #define EBE_PRED_SNAPSHOT 2  /* AB4 + regional snapshot map (Sec. 3.2) */
+#define EBE_PRED_LEARNED 3   /* two candidates: the kind-2 guess and the AB4
+                                increment plus a node-wise network estimate of
+                                its error (see "Learned predictor" below); the
+                                one with the smaller initial residual is kept
+                                (ties keep the kind-2 guess).  The network is
+                                used from step 5 on once weights are set;
+                                after 8 consecutive steps that kept the kind-2
+                                guess it is evaluated only on steps divisible
+                                by 16 until it wins again. */
 
 /* Precision of the refinement.  FP64: Algorithm 1 in FP64.  FP32 / BF16: a
  * flexible outer PCG in FP64 (residual, dot products, update; Polak-Ribiere
@@ -118,6 +127,11 @@ typedef struct {
     int32_t status;
     int32_t inner_iters;
     double res0, res_rec, res_true, bnorm;
+    int32_t learned;        /* kind 3: 1 the learned candidate was kept, 0 the snapshot
+                               prediction; -1 if no candidate was evaluated this step */
+    int32_t reserved;
+    double res0_snapshot;   /* kind 3: ||b - A x||/||b|| of both candidates (free rows) */
+    double res0_learned;
 } ebe_step_stats;
 
 /* Version string of the library. */
@@ -221,6 +235,74 @@ int ebe_kernel_time(ebe_handle* h, int64_t* launches, double* mean_ms);
 /* Sizes used for roofline accounting of one PCG iteration: n_nodes, n_elems,
  * n_patch_nodes (sum over patches of the nodes each patch touches), patches. */
 int ebe_sizes(ebe_handle* h, int64_t* n_nodes, int64_t* n_elems, int64_t* n_patch_nodes, int64_t* n_patches);
+
+/* Changes the predictor kind (EBE_PRED_*) of later steps. */
+int ebe_set_predictor(ebe_handle* h, int32_t kind);
+
+/* Back to rest: u = v = a = 0, empty velocity history and snapshot ring,
+ * it = 0.  The mesh, the network weights and the collected samples stay. */
+int ebe_reset(ebe_handle* h);
+
+/* ---- Learned predictor ---------------------------------------------------
+ * Not in the paper (which mentions learned surrogates only as related work,
+ * Sec. 1): an extension of the predictor of Sec. 3.2 (Eq. predictor, whose
+ * guess may use the force f of the new step).  A network applied node by
+ * node, 15 -> 64 -> 64 -> 3 with GELU (tanh form) after each hidden layer,
+ * estimates the error of the Adams-Bashforth increment, du - du_AB (the
+ * quantity the snapshot map predicts from past errors).  Inputs of node n for
+ * step it: its last four displacements, encoded as u^{it-1} (divided by
+ * scales[0]) and the increments u^{it-1} - u^{it-2}, u^{it-2} - u^{it-3},
+ * u^{it-3} - u^{it-4} (divided by scales[1]; the same information without the
+ * cancellation BF16 inputs would cause), then its external force f^{it}
+ * (divided by scales[2]); the estimate is scales[3] times the output (zero on
+ * fixed dofs).
+ * Inference uses BF16 weights and activations with FP32 accumulation (MFMA).
+ * Training (FP32 with BF16-rounded weights and inputs in the forward, Adam
+ * with beta1 = 0.9, beta2 = 0.999, eps = 1e-8) minimises the mean squared
+ * error between the output and (du^{it} - du_AB^{it}) / scales[3] over samples
+ * collected during ebe_step (steps 5 and later).
+ * Parameter vector (FP32, 5379 values): W1[64][15], b1[64], W2[64][64],
+ * b2[64], W3[3][64], b3[3], row-major; layer k computes W_k h + b_k.
+ * ebe_assemble drops weights and samples. */
+#define EBE_MLP_IN 15
+#define EBE_MLP_HIDDEN 64
+#define EBE_MLP_OUT 3
+#define EBE_MLP_PARAMS 5379
+#define EBE_MLP_SAMPLE 18     /* floats per collected sample: 15 raw inputs, 3 raw targets */
+#define EBE_MLP_SCALES 4
+#define EBE_MLP_MAX_BATCH 8192
+
+/* Sets the FP32 master weights (host [5379]) and scales (host [4], > 0);
+ * resets the Adam moments and step count. */
+int ebe_mlp_set(ebe_handle* h, const float* params, const float* scales);
+/* Reads the FP32 master weights (host [5379] or NULL) and scales (host [4] or NULL). */
+int ebe_mlp_get(ebe_handle* h, float* params, float* scales);
+/* Inference kernel on given inputs: x device [n][15] (already scaled), y
+ * device [n][3] (network outputs, unscaled).  With predictor kind 3,
+ * ebe_predict returns the learned candidate (f_next: the force of the new
+ * step, device [3N], or NULL for zero). */
+int ebe_mlp_forward(ebe_handle* h, int64_t n, const float* x, float* y);
+/* Loss and gradient over n (1..8192) samples: x device [n][15], t device
+ * [n][3] (scaled targets); grad device [5379] out; loss host out or NULL. */
+int ebe_mlp_grad(ebe_handle* h, int64_t n, const float* x, const float* t, float* grad, double* loss);
+/* One Adam step of the master weights with the given gradient (device [5379]). */
+int ebe_mlp_adam(ebe_handle* h, const float* grad, float lr);
+/* Sample collection: every later ebe_step from step 5 on appends one sample
+ * per listed node (device int32 [k], caller's node ids) while `capacity`
+ * samples fit.  A capacity different from the current one
+ * drops the samples collected so far.  nodes NULL or k = 0 stops collecting. */
+int ebe_collect(ebe_handle* h, int64_t capacity, const int32_t* nodes, int32_t k);
+/* Number of collected samples; copies them to dst (device [count][18]) if not NULL. */
+int ebe_samples(ebe_handle* h, int64_t* count, float* dst);
+/* Sets the scales to the root mean squares of the collected inputs of each
+ * group (newest displacement, increments, force) and of the targets (a zero
+ * RMS gives 1); returns them in scales (host [4]) if not NULL.  A later ebe_mlp_set replaces them with the
+ * scales it is given. */
+int ebe_mlp_fit_scales(ebe_handle* h, float* scales);
+/* `steps` Adam steps on minibatches of the collected samples: idx device
+ * int64 [steps][batch], every entry in 0..count-1 (checked); loss host
+ * [steps] receives each minibatch's loss, or NULL. */
+int ebe_mlp_train(ebe_handle* h, int32_t steps, int32_t batch, const int64_t* idx, float lr, double* loss);
 
 /* The configuration in effect (defaults filled in for fields given as <= 0).
  * out: host struct written by the call.  EBE_E_INVALID_ARG if out is NULL. */

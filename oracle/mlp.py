@@ -2,9 +2,11 @@
 
 Not part of the paper's method: the paper names learned surrogates only as
 related work (Sec. 1).  The extension built on top of the predictor of
-Sec. 3.2 is a small per-node network whose output corrects the snapshot
-prediction of the next increment; CG refinement (Algorithm 1) still decides
-the answer, so the network changes the iteration count only.
+Sec. 3.2 is a small per-node network that estimates the error of the
+Adams-Bashforth increment (the quantity the snapshot map predicts from past
+errors) from the node's displacement history and the force of the new step;
+CG refinement (Algorithm 1) still decides the answer, so the network changes
+the iteration count only.
 
 Definitions followed here (plain NumPy, float64, no blocking or fusion):
   * network: y = W3 g(W2 g(W1 x + b1) + b2) + b3 with x in R^15, hidden
@@ -14,10 +16,11 @@ Definitions followed here (plain NumPy, float64, no blocking or fusion):
     W3[3][64], b3[3], row-major;
   * loss over a batch of B samples: L = 1/(3B) sum_b sum_o (y_bo - t_bo)^2;
   * Adam (Kingma & Ba, Algorithm 1) with bias-corrected moments;
-  * features of node n for step it: the displacements u^{it-1}, u^{it-2},
-    u^{it-3}, u^{it-4} of the node (3 values each) divided by s_u, then the
-    node's external force f^{it} divided by s_f; the target is the error of
-    the snapshot prediction, (du^{it} - xbar^{it}) / s_t.
+  * features of node n for step it, from its displacements u^{it-1..it-4}
+    and force f^{it}: u^{it-1} / s_u, the increments (u^{it-1} - u^{it-2},
+    u^{it-2} - u^{it-3}, u^{it-3} - u^{it-4}) / s_d, f^{it} / s_f (3 values
+    each); the target is the error of the Adams-Bashforth increment,
+    (du^{it} - du_AB^{it}) / s_t.
 Weights are used in BF16 by the method; bf16_round gives those values
 (round to nearest even of the float32 value).
 """
@@ -110,15 +113,16 @@ def bf16_round(x):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def features(u_hist, f, s_u, s_f):
+def features(u_hist, f, s_u, s_d, s_f):
     """Per-node inputs [N][15] from the displacements u^{it-1..it-4} (list of
     four [3N] vectors, newest first) and the force f^{it} ([3N])."""
-    cols = [np.asarray(u, dtype=np.float64).reshape(-1, 3) / s_u for u in u_hist]
+    u = [np.asarray(x, dtype=np.float64).reshape(-1, 3) for x in u_hist]
+    cols = [u[0] / s_u] + [(u[q] - u[q + 1]) / s_d for q in range(3)]
     cols.append(np.asarray(f, dtype=np.float64).reshape(-1, 3) / s_f)
     return np.concatenate(cols, axis=1)
 
 
 def correction(params, X, s_t):
-    """Correction of the snapshot prediction, [N][3] (s_t times the outputs)."""
+    """Estimate of the Adams-Bashforth error, [N][3] (s_t times the outputs)."""
     Y, _ = forward(params, X)
     return s_t * Y

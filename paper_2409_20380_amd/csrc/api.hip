@@ -82,6 +82,29 @@ struct ebe_handle {
     double* pap_in = nullptr;
     double* res_in = nullptr;
     int par_in = 0;
+    // learned predictor (allocated on first use; dropped by ebe_assemble)
+    double* msum = nullptr;          // [N] row sums of M
+    double* x_alt = nullptr;         // [3N] learned candidate
+    double* cand_part = nullptr;     // [2][res_grid] candidate residual partials
+    double* qbuf_alt = nullptr;      // matvec slots of the learned candidate
+    bool q_ready = false;            // qbuf already holds A x for the next solve's guess
+    uint16_t* mlp_w = nullptr;       // BF16 weights
+    float *mlp_wm = nullptr, *mlp_m = nullptr, *mlp_v = nullptr;
+    float mlp_scales[kMlpScales] = {1.0f, 1.0f, 1.0f, 1.0f};
+    int cand_losses = 0;             // consecutive steps the learned candidate lost
+    bool mlp_ready = false;
+    int mlp_t = 0;                   // Adam steps taken
+    MlpTrain tr{};
+    int tr_cap = 0;                  // batch capacity of the training scratch
+    double* tr_loss = nullptr;
+    int tr_loss_cap = 0;
+    float* samples = nullptr;        // [samples_cap][kMlpSample]
+    int64_t samples_cap = 0, samples_n = 0;
+    int32_t* coll_nodes = nullptr;   // internal ids of the sampled nodes
+    double* coll_stage = nullptr;
+    int coll_k = 0, coll_cap_k = 0;
+    double* rms3 = nullptr;
+    int32_t* flag = nullptr;
     // kernel timing
     int timing_every = 0;
     int64_t pcg_launches = 0;
@@ -121,6 +144,24 @@ struct ebe_handle {
         for (auto e : ev_free) (void)hipEventDestroy(e);
         ev_free.clear();
         assembled = false;
+        msum = x_alt = cand_part = qbuf_alt = nullptr;
+        q_ready = false;
+        cand_losses = 0;
+        mlp_w = nullptr;
+        mlp_wm = mlp_m = mlp_v = nullptr;
+        mlp_ready = false;
+        mlp_t = 0;
+        tr = MlpTrain{};
+        tr_cap = 0;
+        tr_loss = nullptr;
+        tr_loss_cap = 0;
+        samples = nullptr;
+        samples_cap = samples_n = 0;
+        coll_nodes = nullptr;
+        coll_stage = nullptr;
+        coll_k = coll_cap_k = 0;
+        rms3 = nullptr;
+        flag = nullptr;
     }
 };
 
@@ -247,7 +288,8 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
     const int g_res = res_grid(h->T.n_nodes);
     const int g_pap = pcg_ebe_grid(h->dp);
     auto slot = [&](int j) { return h->res_part + (size_t)(j & 1) * kResArrays * g_res; };
-    launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
+    if (!h->q_ready) launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
+    h->q_ready = false;
     launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(0), 0);
     check_launch();
     int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters - 2);
@@ -312,7 +354,8 @@ int solve_mixed(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) 
     const int g_pap = pcg_ebe_grid(h->dp);
     auto slot = [&](int j) { return h->res_part + (size_t)(j & 1) * kResArrays * g_res; };
     auto islot = [&](int i) { return h->res_in + (size_t)(i & 1) * kResArrays * g_res; };
-    launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
+    if (!h->q_ready) launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf);
+    h->q_ready = false;
     launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(0), 0);
     check_launch();
     int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(1, h->last_iters - 1);
@@ -377,7 +420,7 @@ int run_solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
 }
 
 int snapshot_columns(const ebe_handle* h, int n) {
-    if (h->cfg.predictor != EBE_PRED_SNAPSHOT || h->cfg.s < 1) return 0;
+    if ((h->cfg.predictor != EBE_PRED_SNAPSHOT && h->cfg.predictor != EBE_PRED_LEARNED) || h->cfg.s < 1) return 0;
     int s_eff = std::min(h->cfg.s, n - 2);
     return s_eff >= 1 ? s_eff : 0;
 }
@@ -410,6 +453,108 @@ void rhs_into(ebe_handle* h, const double* f_int, const double* g, double* b) {
                    g2, h->qbuf);
     launch_rhs_finalize(h->stream, h->dn, h->qbuf, f_int, b);
     check_launch();
+}
+
+MlpState mlp_state(ebe_handle* h, const double* f_int, const double* g) {
+    MlpState S{};
+    S.u = h->u;
+    S.v1 = h->vslot(0); S.v2 = h->vslot(1); S.v3 = h->vslot(2); S.v4 = h->vslot(3);
+    S.hdt = 0.5 * h->cfg.dt;
+    S.msum = h->msum;
+    S.g0 = g ? g[0] : 0.0; S.g1 = g ? g[1] : 0.0; S.g2 = g ? g[2] : 0.0;
+    S.f_int = f_int;
+    for (int g = 0; g < 3; ++g) S.inv_s[g] = 1.0 / h->mlp_scales[g];
+    S.s_t = h->mlp_scales[3];
+    S.fixmask = h->dn.fixmask;
+    return S;
+}
+
+// First step whose four displacement inputs are all past the rest state.
+constexpr int kLearnFirstStep = 5;
+
+bool learned_due(const ebe_handle* h, int n) {
+    return h->cfg.predictor == EBE_PRED_LEARNED && h->mlp_ready && n >= kLearnFirstStep;
+}
+
+void need_x_alt(ebe_handle* h) {
+    if (!h->x_alt) h->x_alt = h->alloc<double>(h->n3());
+    if (!h->cand_part) h->cand_part = h->alloc<double>(2 * (size_t)res_grid(h->T.n_nodes));
+    if (!h->qbuf_alt) h->qbuf_alt = h->alloc<double>(3 * h->T.patch_nodes.size());
+}
+
+// After this many consecutive steps in which the kind-2 guess was kept, the
+// learned candidate is evaluated only on every kCandProbe-th step until it
+// wins again (its evaluation costs two matvecs and an inference).
+constexpr int kCandPatience = 8;
+constexpr int kCandProbe = 16;
+
+// Learned candidate = Adams-Bashforth increment (dab) + network estimate of
+// its error; keep whichever of it and the snapshot prediction (in x) has the
+// smaller initial residual ||b - A x||, in x.
+void choose_learned(ebe_handle* h, const double* f_int, const double* g) {
+    hipStream_t s = h->stream;
+    need_x_alt(h);
+    MlpState S = mlp_state(h, f_int, g);
+    S.xs = h->dab;
+    S.xl = h->x_alt;
+    launch_mlp_infer_state(s, h->mlp_w, S, h->T.n_nodes);
+    const int gr = res_grid(h->T.n_nodes);
+    launch_ebe_apply(s, h->dp, h->x, true, h->cM, h->cK, h->qbuf);
+    launch_cand_res(s, h->dn, h->qbuf, h->b, h->cand_part);
+    launch_ebe_apply(s, h->dp, h->x_alt, true, h->cM, h->cK, h->qbuf_alt);
+    launch_cand_res(s, h->dn, h->qbuf_alt, h->b, h->cand_part + gr);
+    launch_cand_select(s, h->dn, h->cand_part, h->cand_part + gr, h->x, h->x_alt, h->qbuf, h->qbuf_alt,
+                       (int64_t)(3 * h->T.patch_nodes.size()), h->sc);
+    check_launch();
+    h->q_ready = true;   // qbuf holds the kept guess's matvec: the solve skips its first one
+}
+
+void need_mlp(ebe_handle* h) {
+    if (!h->mlp_w) {
+        h->mlp_w = h->alloc<uint16_t>(kMlpParams);
+        h->mlp_wm = h->alloc<float>(kMlpParams);
+        h->mlp_m = h->alloc<float>(kMlpParams);
+        h->mlp_v = h->alloc<float>(kMlpParams);
+    }
+    if (!h->flag) h->flag = h->alloc<int32_t>(1);
+    if (!h->tr_loss) {
+        h->tr_loss_cap = 1;
+        h->tr_loss = h->alloc<double>(1);
+    }
+    h->tr.w = h->mlp_w;
+    h->tr.wm = h->mlp_wm;
+    h->tr.m = h->mlp_m;
+    h->tr.v = h->mlp_v;
+}
+
+void need_train(ebe_handle* h, int B) {
+    need_mlp(h);
+    if (B > h->tr_cap) {
+        MlpTrain& T = h->tr;
+        const size_t b = (size_t)B;
+        T.X = h->alloc<float>(kMlpIn * b);
+        T.Z1 = h->alloc<float>(kMlpHid * b);
+        T.H1 = h->alloc<float>(kMlpHid * b);
+        T.Z2 = h->alloc<float>(kMlpHid * b);
+        T.H2 = h->alloc<float>(kMlpHid * b);
+        T.dY = h->alloc<float>(kMlpOut * b);
+        T.dZ1 = h->alloc<float>(kMlpHid * b);
+        T.dZ2 = h->alloc<float>(kMlpHid * b);
+        T.loss_part = h->alloc<float>((b + 255) / 256);
+        if (!T.grad) T.grad = h->alloc<float>(kMlpParams);
+        h->tr_cap = B;
+    }
+}
+
+void need_ready(const ebe_handle* h) {
+    if (!h->mlp_ready) throw State{"no network weights: call ebe_mlp_set first"};
+}
+
+int32_t read_flag(ebe_handle* h) {
+    int32_t f = 0;
+    HIPCHK(hipMemcpyAsync(&f, h->flag, sizeof(f), hipMemcpyDeviceToHost, h->stream));
+    sync_stream(h);
+    return f;
 }
 
 }  // namespace
@@ -546,6 +691,11 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         launch_ebe_diag(s, h->dp, h->cM, h->cK, h->qbuf);
         launch_diag_finalize(s, h->dn, h->qbuf, h->binv6);
         if (h->binv_in) launch_to_f32(s, 6 * N, h->binv6, static_cast<float*>(h->binv_in));
+        // row sums of M: the base-motion force of a node is -msum * g
+        h->msum = h->alloc<double>(N);
+        launch_fill(s, n3, 1.0, h->t0);
+        launch_ebe_apply(s, h->dp, h->t0, false, 1.0, 0.0, h->qbuf);
+        launch_msum(s, h->dn, h->qbuf, h->msum);
         // rest state
         launch_zero(s, n3, h->u);
         launch_zero(s, n3, h->a);
@@ -636,12 +786,25 @@ int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* 
 }
 
 int ebe_predict(ebe_handle* h, const double* f_next, double* dxbar, int32_t* s_eff) {
-    (void)f_next;
     return guarded(h, [&]() -> int {
         need_assembled(h);
         need_ptr(dxbar, "dxbar");
         int se = predict_into(h, h->t1);
-        to_user(h, h->t1, dxbar);
+        if (learned_due(h, h->it + 1)) {
+            const double* f_int = nullptr;
+            if (f_next) {
+                to_internal(h, f_next, h->t0);
+                f_int = h->t0;
+            }
+            need_x_alt(h);
+            MlpState S = mlp_state(h, f_int, nullptr);
+            S.xs = h->dab;
+            S.xl = h->x_alt;
+            launch_mlp_infer_state(h->stream, h->mlp_w, S, h->T.n_nodes);
+            to_user(h, h->x_alt, dxbar);
+        } else {
+            to_user(h, h->t1, dxbar);
+        }
         check_launch();
         if (s_eff) *s_eff = se;
         return EBE_OK;
@@ -675,9 +838,20 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
         rhs_into(h, f_int, base_acc, h->b);
         const int n = h->it + 1;
         int s_eff = predict_into(h, h->x);
+        const bool collect = h->coll_k > 0 && n >= kLearnFirstStep && h->samples_n + h->coll_k <= h->samples_cap;
+        if (collect) launch_collect_pre(s, h->coll_nodes, h->coll_k, h->dab, h->coll_stage);
+        const bool learned = learned_due(h, n) && (h->cand_losses < kCandPatience || n % kCandProbe == 0);
+        if (learned) choose_learned(h, f_int, base_acc);
         ebe_solve_stats st{};
         int rc = run_solve(h, h->b, h->x, &st);
         if (rc < 0) return rc;
+        if (learned) h->cand_losses = h->sc_host->cand_pick ? 0 : h->cand_losses + 1;
+        if (collect) {
+            MlpState S = mlp_state(h, f_int, base_acc);
+            launch_collect_post(s, S, h->coll_nodes, h->coll_k, h->x, h->coll_stage,
+                                h->samples + h->samples_n * kMlpSample);
+            h->samples_n += h->coll_k;
+        }
         double* slot = h->cfg.s >= 1 ? h->ring_slot((n - 1) % (h->cfg.s + 1)) : nullptr;
         launch_newmark(s, h->n3(), h->cfg.dt, h->x, h->dab, h->u, h->vslot(0), h->vslot(3), h->a, slot);
         check_launch();
@@ -694,6 +868,16 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
             stats->res_rec = st.res_rec;
             stats->res_true = st.res_true;
             stats->bnorm = st.bnorm;
+            stats->learned = -1;
+            stats->res0_snapshot = stats->res0_learned = 0.0;
+            if (learned) {
+                const DevScalars& S = *h->sc_host;
+                stats->learned = S.cand_pick;
+                if (st.bnorm > 0) {
+                    stats->res0_snapshot = std::sqrt(S.cand_rr[0]) / st.bnorm;
+                    stats->res0_learned = std::sqrt(S.cand_rr[1]) / st.bnorm;
+                }
+            }
         }
         return rc;
     });
@@ -784,6 +968,215 @@ int ebe_sizes(ebe_handle* h, int64_t* n_nodes, int64_t* n_elems, int64_t* n_patc
         if (n_elems) *n_elems = h->T.n_elems;
         if (n_patch_nodes) *n_patch_nodes = (int64_t)h->T.patch_nodes.size();
         if (n_patches) *n_patches = h->T.n_patches;
+        return EBE_OK;
+    });
+}
+
+int ebe_set_predictor(ebe_handle* h, int32_t kind) {
+    return guarded(h, [&]() -> int {
+        if (kind < EBE_PRED_ZERO || kind > EBE_PRED_LEARNED) throw Arg{"predictor kind must be 0..3"};
+        h->cfg.predictor = kind;
+        return EBE_OK;
+    });
+}
+
+int ebe_reset(ebe_handle* h) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        hipStream_t s = h->stream;
+        const int64_t n3 = h->n3();
+        launch_zero(s, n3, h->u);
+        launch_zero(s, n3, h->a);
+        for (int k = 0; k < 4; ++k) launch_zero(s, n3, h->vh[k]);
+        launch_zero(s, (int64_t)(h->cfg.s + 1) * n3, h->ring);
+        check_launch();
+        h->head = 0;
+        h->it = 0;
+        h->last_iters = 0;
+        h->cand_losses = 0;
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_set(ebe_handle* h, const float* params, const float* scales) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        need_ptr(params, "params");
+        need_ptr(scales, "scales");
+        for (int i = 0; i < kMlpParams; ++i)
+            if (!std::isfinite(params[i])) throw Arg{"non-finite network parameter"};
+        for (int i = 0; i < kMlpScales; ++i)
+            if (!(scales[i] > 0.0f) || !std::isfinite(scales[i])) throw Arg{"scales must be positive and finite"};
+        need_mlp(h);
+        hipStream_t s = h->stream;
+        HIPCHK(hipMemcpyAsync(h->mlp_wm, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemsetAsync(h->mlp_m, 0, kMlpParams * sizeof(float), s));
+        HIPCHK(hipMemsetAsync(h->mlp_v, 0, kMlpParams * sizeof(float), s));
+        launch_mlp_round(s, h->mlp_wm, h->mlp_w);
+        check_launch();
+        sync_stream(h);
+        std::copy(scales, scales + kMlpScales, h->mlp_scales);
+        h->mlp_t = 0;
+        h->mlp_ready = true;
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_get(ebe_handle* h, float* params, float* scales) {
+    return guarded(h, [&]() -> int {
+        need_ready(h);
+        if (params) {
+            HIPCHK(hipMemcpyAsync(params, h->mlp_wm, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+            sync_stream(h);
+        }
+        if (scales) std::copy(h->mlp_scales, h->mlp_scales + kMlpScales, scales);
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_forward(ebe_handle* h, int64_t n, const float* x, float* y) {
+    return guarded(h, [&]() -> int {
+        need_ready(h);
+        if (n < 0) throw Arg{"n must be non-negative"};
+        if (n == 0) return EBE_OK;
+        need_ptr(x, "x");
+        need_ptr(y, "y");
+        launch_mlp_infer_array(h->stream, h->mlp_w, n, x, y);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_grad(ebe_handle* h, int64_t n, const float* x, const float* t, float* grad, double* loss) {
+    return guarded(h, [&]() -> int {
+        need_ready(h);
+        if (n < 1 || n > kMlpMaxBatch) throw Arg{"n must be in 1..8192"};
+        need_ptr(x, "x");
+        need_ptr(t, "t");
+        need_ptr(grad, "grad");
+        need_train(h, (int)n);
+        MlpTrain T = h->tr;
+        T.x_in = x;
+        T.t_in = t;
+        launch_mlp_grads(h->stream, T, (int)n, nullptr);
+        HIPCHK(hipMemcpyAsync(grad, T.grad, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, h->stream));
+        launch_mlp_loss(h->stream, T, (int)n, h->tr_loss);
+        check_launch();
+        double l = 0.0;
+        HIPCHK(hipMemcpyAsync(&l, h->tr_loss, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        sync_stream(h);
+        if (loss) *loss = l;
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_adam(ebe_handle* h, const float* grad, float lr) {
+    return guarded(h, [&]() -> int {
+        need_ready(h);
+        need_ptr(grad, "grad");
+        if (!(lr > 0.0f) || !std::isfinite(lr)) throw Arg{"lr must be positive"};
+        need_mlp(h);
+        h->mlp_t += 1;
+        launch_mlp_adam(h->stream, h->tr, grad, lr, h->mlp_t, 0, nullptr, 0);
+        check_launch();
+        return EBE_OK;
+    });
+}
+
+int ebe_collect(ebe_handle* h, int64_t capacity, const int32_t* nodes, int32_t k) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (!nodes || k == 0) {
+            h->coll_k = 0;
+            return EBE_OK;
+        }
+        if (k < 0 || k > h->T.n_nodes) throw Arg{"k must be in 0..n_nodes"};
+        if (capacity < k) throw Arg{"capacity must hold at least one step of samples"};
+        need_mlp(h);
+        hipStream_t s = h->stream;
+        if (capacity != h->samples_cap) {
+            h->samples = h->alloc<float>((size_t)capacity * kMlpSample);
+            h->samples_cap = capacity;
+            h->samples_n = 0;
+        }
+        if (k > h->coll_cap_k) {
+            h->coll_nodes = h->alloc<int32_t>(k);
+            h->coll_stage = h->alloc<double>(3 * (size_t)k);
+            h->coll_cap_k = k;
+        }
+        launch_map_nodes(s, nodes, k, h->d_u2i, h->T.n_nodes, h->coll_nodes, h->flag);
+        check_launch();
+        if (read_flag(h)) throw Arg{"node id out of range"};
+        h->coll_k = k;
+        return EBE_OK;
+    });
+}
+
+int ebe_samples(ebe_handle* h, int64_t* count, float* dst) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (count) *count = h->samples_n;
+        if (dst && h->samples_n > 0) {
+            HIPCHK(hipMemcpyAsync(dst, h->samples, (size_t)h->samples_n * kMlpSample * sizeof(float),
+                                  hipMemcpyDeviceToDevice, h->stream));
+            check_launch();
+        }
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_fit_scales(ebe_handle* h, float* scales) {
+    return guarded(h, [&]() -> int {
+        need_assembled(h);
+        if (h->samples_n < 1) throw State{"no samples collected"};
+        if (!h->rms3) h->rms3 = h->alloc<double>(kMlpScales);
+        launch_sample_rms(h->stream, h->samples, h->samples_n, h->rms3);
+        check_launch();
+        double r[kMlpScales];
+        HIPCHK(hipMemcpyAsync(r, h->rms3, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+        sync_stream(h);
+        for (int i = 0; i < kMlpScales; ++i) {
+            if (!std::isfinite(r[i])) throw Arg{"non-finite samples"};
+            h->mlp_scales[i] = r[i] > 0.0 ? (float)r[i] : 1.0f;
+        }
+        if (scales) std::copy(h->mlp_scales, h->mlp_scales + kMlpScales, scales);
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_train(ebe_handle* h, int32_t steps, int32_t batch, const int64_t* idx, float lr, double* loss) {
+    return guarded(h, [&]() -> int {
+        need_ready(h);
+        if (steps < 0) throw Arg{"steps must be non-negative"};
+        if (batch < 1 || batch > kMlpMaxBatch) throw Arg{"batch must be in 1..8192"};
+        if (!(lr > 0.0f) || !std::isfinite(lr)) throw Arg{"lr must be positive"};
+        if (steps == 0) return EBE_OK;
+        need_ptr(idx, "idx");
+        if (h->samples_n < 1) throw State{"no samples collected"};
+        need_train(h, batch);
+        hipStream_t s = h->stream;
+        launch_check_index(s, idx, (int64_t)steps * batch, h->samples_n, h->flag);
+        check_launch();
+        if (read_flag(h)) throw Arg{"sample index out of range"};
+        if (steps > h->tr_loss_cap) {
+            h->tr_loss = h->alloc<double>(steps);
+            h->tr_loss_cap = steps;
+        }
+        MlpTrain T = h->tr;
+        T.samples = h->samples;
+        T.n_samples = h->samples_n;
+        for (int g = 0; g < 3; ++g) T.inv_s[g] = 1.0f / h->mlp_scales[g];
+        T.inv_st = 1.0f / h->mlp_scales[3];
+        for (int k = 0; k < steps; ++k) {
+            launch_mlp_grads(s, T, batch, idx + (int64_t)k * batch);
+            h->mlp_t += 1;
+            launch_mlp_adam(s, T, T.grad, lr, h->mlp_t, batch, h->tr_loss, k);
+        }
+        check_launch();
+        if (loss) {
+            HIPCHK(hipMemcpyAsync(loss, h->tr_loss, steps * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        sync_stream(h);
         return EBE_OK;
     });
 }

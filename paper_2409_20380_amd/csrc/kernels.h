@@ -22,6 +22,11 @@ struct DevScalars {
     int32_t checked;  // true residual evaluated since the loop stopped
     int32_t cycle_start;  // trip index at which the current CG cycle began (beta = 0 there)
     int32_t inner_iters;  // mixed precision: inner trips summed over the solve
+    // learned predictor: squared free-row residuals of the snapshot (0) and
+    // learned (1) candidates and which one was kept; not reset by a solve
+    double cand_rr[2];
+    int32_t cand_pick;
+    int32_t pad_;
 };
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_NONFINITE = 2, DONE_MAXITER = 3, DONE_ZERO_RHS = 4 };
@@ -154,5 +159,68 @@ void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, cons
                     const double* v_old, double* v_new, double* a, double* ring_slot);
 void launch_gather3(hipStream_t s, int64_t n, const int32_t* idx, const double* in, double* out);
 void launch_zero(hipStream_t s, int64_t count, double* p);
+
+// ---- learned node-wise predictor (mlp.hip)
+constexpr int kMlpIn = 15, kMlpHid = 64, kMlpOut = 3;
+constexpr int kMlpParams = kMlpHid * kMlpIn + kMlpHid + kMlpHid * kMlpHid + kMlpHid + kMlpOut * kMlpHid + kMlpOut;
+constexpr int kMlpSample = kMlpIn + kMlpOut;   // one collected sample: 15 raw features + 3 raw targets
+constexpr int kMlpScales = 4;                   // newest displacement, increments, force, target
+// Input group of feature k: 0 displacement u^{it-1}, 1 increments, 2 force.
+__host__ __device__ constexpr int mlp_group(int k) { return k < 3 ? 0 : (k < 12 ? 1 : 2); }
+constexpr int kMlpMaxBatch = 8192;
+// Solver state read by the in-step inference and the sample collection.
+struct MlpState {
+    const double* u;                              // u^{it-1}
+    const double *v1, *v2, *v3, *v4;              // v^{it-1} .. v^{it-4}
+    double hdt;                                   // dt / 2
+    const double* msum;                           // [N] row sums of M (base-motion force)
+    double g0, g1, g2;                            // base acceleration of the step
+    const double* f_int;                          // extra external force (internal order) or null
+    double inv_s[3];                              // 1 / scale of each input group
+    double s_t;                                   // output scale
+    const uint8_t* fixmask;
+    const double* xs;                             // base of the candidate (Adams-Bashforth increment)
+    double* xl;                                   // learned candidate xs + s_t * output (out)
+};
+// Training buffers (batch-major activations are stored [feature][B]).
+struct MlpTrain {
+    uint16_t* w;                                  // BF16 weights used by every forward
+    float *wm, *m, *v;                            // FP32 master weights and Adam moments
+    const float* samples;                         // collected rows of kMlpSample floats
+    int64_t n_samples;
+    float inv_s[3], inv_st;
+    const float *x_in, *t_in;                     // explicit scaled inputs / targets (gradient checks)
+    float *X, *Z1, *H1, *Z2, *H2, *dY, *dZ1, *dZ2;
+    float* loss_part;
+    float* grad;                                  // [kMlpParams]
+};
+// Row sums of M (x component of M 1) per node, from an unmasked M-only matvec.
+void launch_msum(hipStream_t s, const DevNodes& N, const double* qbuf, double* msum);
+// Candidate selection of the learned predictor: free-row ||b - A x||^2
+// partials of a candidate (slot sums in qbuf), then keep the candidate with
+// the smaller residual in x and its matvec slots in qbuf (ties keep the
+// snapshot prediction).
+void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, double* part);
+void launch_cand_select(hipStream_t s, const DevNodes& N, const double* part_s, const double* part_l, double* x,
+                        const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc);
+void launch_fill(hipStream_t s, int64_t n, double value, double* p);
+void launch_mlp_infer_array(hipStream_t s, const uint16_t* w, int64_t n, const float* x, float* y);
+void launch_mlp_infer_state(hipStream_t s, const uint16_t* w, const MlpState& S, int64_t n);
+// Forward + backward + weight gradients (into T.grad) over B samples: rows
+// idx of the collected samples when idx is set, else T.x_in / T.t_in.
+void launch_mlp_grads(hipStream_t s, const MlpTrain& T, int B, const int64_t* idx);
+// One Adam step (step number t >= 1) with gradient grad; if loss is set, also
+// writes the loss of the last forward over B samples to loss[step].
+void launch_mlp_adam(hipStream_t s, const MlpTrain& T, const float* grad, float lr, int t, int B, double* loss,
+                     int step);
+void launch_mlp_loss(hipStream_t s, const MlpTrain& T, int B, double* loss);
+void launch_mlp_round(hipStream_t s, const float* wm, uint16_t* wb);
+void launch_collect_pre(hipStream_t s, const int32_t* nodes, int k, const double* xs, double* stage);
+void launch_collect_post(hipStream_t s, const MlpState& S, const int32_t* nodes, int k, const double* du,
+                         const double* stage, float* out);
+void launch_sample_rms(hipStream_t s, const float* samples, int64_t count, double* out4);
+void launch_map_nodes(hipStream_t s, const int32_t* user, int k, const int32_t* u2i, int64_t n, int32_t* out,
+                      int32_t* flag);
+void launch_check_index(hipStream_t s, const int64_t* idx, int64_t m, int64_t limit, int32_t* flag);
 
 }  // namespace ebe

@@ -1086,6 +1086,75 @@ void launch_to_f32(hipStream_t s, int64_t n, const double* in, float* out) {
 }
 
 // ---------------------------------------------------------------------------
+// learned-predictor support: M row sums, candidate residuals and selection
+// ---------------------------------------------------------------------------
+__global__ void k_msum(DevNodes N, const double* qbuf, double* msum) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N.n) return;
+    double q0, q1, q2;
+    gather_q(N, qbuf, n, q0, q1, q2);
+    msum[n] = q0;
+}
+
+void launch_msum(hipStream_t s, const DevNodes& N, const double* qbuf, double* msum) {
+    hipLaunchKernelGGL(k_msum, dim3((unsigned)((N.n + 255) / 256)), dim3(256), 0, s, N, qbuf, msum);
+}
+
+__global__ __launch_bounds__(256) void k_cand_res(DevNodes N, const double* qbuf, const double* b, double* part) {
+    double v = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
+        double q0, q1, q2;
+        gather_q(N, qbuf, n, q0, q1, q2);
+        const uint8_t fm = N.fixmask[n];
+        const double r0 = (fm & 1) ? 0.0 : b[3 * n] - q0;
+        const double r1 = (fm & 2) ? 0.0 : b[3 * n + 1] - q1;
+        const double r2 = (fm & 4) ? 0.0 : b[3 * n + 2] - q2;
+        v += r0 * r0 + r1 * r1 + r2 * r2;
+    }
+    v = block_bcast_sum(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, double* part) {
+    hipLaunchKernelGGL(k_cand_res, dim3(res_grid(N.n)), dim3(256), 0, s, N, qbuf, b, part);
+}
+
+__global__ __launch_bounds__(256) void k_cand_select(DevNodes N, const double* part_s, const double* part_l, int g,
+                                                     double* x, const double* x_alt, double* qbuf,
+                                                     const double* qbuf_alt, int64_t nq, DevScalars* sc) {
+    double rs = lane_partials<kMaxResGrid / 256>(part_s, g, threadIdx.x, 256);
+    double rl = lane_partials<kMaxResGrid / 256>(part_l, g, threadIdx.x, 256);
+    rs = block_bcast_sum(rs);
+    rl = block_bcast_sum(rl);
+    const bool pick = rl < rs;   // NaN in the learned candidate keeps the snapshot prediction
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->cand_rr[0] = rs;
+        sc->cand_rr[1] = rl;
+        sc->cand_pick = pick ? 1 : 0;
+    }
+    if (!pick) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * N.n; i += stride) x[i] = x_alt[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += stride) qbuf[i] = qbuf_alt[i];
+}
+
+void launch_cand_select(hipStream_t s, const DevNodes& N, const double* part_s, const double* part_l, double* x,
+                        const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc) {
+    const int g = res_grid(N.n);
+    hipLaunchKernelGGL(k_cand_select, dim3(g), dim3(256), 0, s, N, part_s, part_l, g, x, x_alt, qbuf, qbuf_alt, nq,
+                       sc);
+}
+
+__global__ void k_fill(int64_t n, double value, double* p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+void launch_fill(hipStream_t s, int64_t n, double value, double* p) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, value, p);
+}
+
+// ---------------------------------------------------------------------------
 // predictor
 // ---------------------------------------------------------------------------
 // Adams-Bashforth 4-step increment: dab = dt/24 (55 v1 - 59 v2 + 37 v3 - 9 v4);

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libebe.so")
 
 OK, NOT_CONVERGED = 0, 1
 E_INVALID_ARG, E_HIP, E_NO_MEMORY, E_BAD_STATE, E_NONFINITE = -1, -2, -3, -4, -5
-PRED_ZERO, PRED_AB4, PRED_SNAPSHOT = 0, 1, 2
+PRED_ZERO, PRED_AB4, PRED_SNAPSHOT, PRED_LEARNED = 0, 1, 2, 3
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS, MLP_SAMPLE, MLP_MAX_BATCH, MLP_SCALES = 15, 64, 3, 5379, 18, 8192, 4
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 
 
@@ -45,14 +46,17 @@ class SolveStats(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("it", C.c_int32), ("s_eff", C.c_int32), ("iters", C.c_int32), ("restarts", C.c_int32),
                 ("status", C.c_int32), ("inner_iters", C.c_int32), ("res0", C.c_double), ("res_rec", C.c_double),
-                ("res_true", C.c_double), ("bnorm", C.c_double)]
+                ("res_true", C.c_double), ("bnorm", C.c_double), ("learned", C.c_int32), ("reserved", C.c_int32),
+                ("res0_snapshot", C.c_double), ("res0_learned", C.c_double)]
 
 
 # Every symbol include/ebe.h declares (checked by the CPU test suite).
 EXPORTS = ("ebe_version", "ebe_create", "ebe_destroy", "ebe_last_error", "ebe_assemble", "ebe_get_regions",
            "ebe_apply", "ebe_apply_mk", "ebe_precond", "ebe_rhs", "ebe_predict", "ebe_refine", "ebe_step",
            "ebe_get_state", "ebe_set_state", "ebe_get_history", "ebe_set_history", "ebe_sync",
-           "ebe_set_kernel_timing", "ebe_kernel_time", "ebe_sizes", "ebe_get_config")
+           "ebe_set_kernel_timing", "ebe_kernel_time", "ebe_sizes", "ebe_get_config", "ebe_set_predictor",
+           "ebe_reset", "ebe_mlp_set", "ebe_mlp_get", "ebe_mlp_forward", "ebe_mlp_grad", "ebe_mlp_adam",
+           "ebe_collect", "ebe_samples", "ebe_mlp_fit_scales", "ebe_mlp_train")
 
 _lib = None
 vp = C.c_void_p
@@ -93,6 +97,18 @@ def lib():
     L.ebe_kernel_time.argtypes = [vp, i64_p, d_p]
     L.ebe_sizes.argtypes = [vp, i64_p, i64_p, i64_p, i64_p]
     L.ebe_get_config.argtypes = [vp, C.POINTER(Config)]
+    f_p = C.POINTER(C.c_float)
+    L.ebe_set_predictor.argtypes = [vp, C.c_int32]
+    L.ebe_reset.argtypes = [vp]
+    L.ebe_mlp_set.argtypes = [vp, f_p, f_p]
+    L.ebe_mlp_get.argtypes = [vp, f_p, f_p]
+    L.ebe_mlp_forward.argtypes = [vp, C.c_int64, vp, vp]
+    L.ebe_mlp_grad.argtypes = [vp, C.c_int64, vp, vp, vp, d_p]
+    L.ebe_mlp_adam.argtypes = [vp, vp, C.c_float]
+    L.ebe_collect.argtypes = [vp, C.c_int64, vp, C.c_int32]
+    L.ebe_samples.argtypes = [vp, i64_p, vp]
+    L.ebe_mlp_fit_scales.argtypes = [vp, f_p]
+    L.ebe_mlp_train.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_float, d_p]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
     L.ebe_version.restype = C.c_char_p
@@ -108,6 +124,17 @@ def _dev(t):
     import torch
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise TypeError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _devt(t, dtype_name, n=None):
+    """Device pointer of a contiguous CUDA tensor of the given dtype (and length)."""
+    import torch
+    dt = getattr(torch, dtype_name)
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype_name} CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -270,6 +297,77 @@ class Solver:
         c = Config()
         self._check(lib().ebe_get_config(self._h, C.byref(c)))
         return c
+
+    # ---- learned predictor
+    def set_predictor(self, kind):
+        self._check(lib().ebe_set_predictor(self._h, int(kind)))
+        self.cfg.predictor = int(kind)
+
+    def reset(self):
+        self._check(lib().ebe_reset(self._h))
+
+    def mlp_set(self, params, scales):
+        p, pp = _host(params, np.float32, C.POINTER(C.c_float))
+        s, sp = _host(scales, np.float32, C.POINTER(C.c_float))
+        if p.size != MLP_PARAMS or s.size != MLP_SCALES:
+            raise ValueError(f"need {MLP_PARAMS} parameters and {MLP_SCALES} scales")
+        self._check(lib().ebe_mlp_set(self._h, pp, sp))
+
+    def mlp_get(self):
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        s = np.empty(MLP_SCALES, dtype=np.float32)
+        self._check(lib().ebe_mlp_get(self._h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                      s.ctypes.data_as(C.POINTER(C.c_float))))
+        return p, s
+
+    def mlp_forward(self, x):
+        """x: float32 CUDA tensor [n][15] (scaled inputs) -> outputs [n][3]."""
+        import torch
+        n = x.shape[0]
+        y = torch.empty((n, MLP_OUT), dtype=torch.float32, device="cuda")
+        self._check(lib().ebe_mlp_forward(self._h, n, _devt(x, "float32", n * MLP_IN), _devt(y, "float32")))
+        return y
+
+    def mlp_grad(self, x, t):
+        import torch
+        n = x.shape[0]
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        self._check(lib().ebe_mlp_grad(self._h, n, _devt(x, "float32", n * MLP_IN), _devt(t, "float32", n * MLP_OUT),
+                                       _devt(g, "float32"), C.byref(loss)))
+        return g, loss.value
+
+    def mlp_adam(self, grad, lr):
+        self._check(lib().ebe_mlp_adam(self._h, _devt(grad, "float32", MLP_PARAMS), float(lr)))
+
+    def collect(self, capacity, nodes=None):
+        """Collect samples at the listed nodes (int32 CUDA tensor of node ids) during later steps."""
+        if nodes is None:
+            self._check(lib().ebe_collect(self._h, int(capacity), None, 0))
+        else:
+            self._check(lib().ebe_collect(self._h, int(capacity), _devt(nodes, "int32"), int(nodes.numel())))
+
+    def samples(self):
+        import torch
+        n = C.c_int64()
+        self._check(lib().ebe_samples(self._h, C.byref(n), None))
+        out = torch.empty((n.value, MLP_SAMPLE), dtype=torch.float32, device="cuda")
+        if n.value:
+            self._check(lib().ebe_samples(self._h, C.byref(n), _devt(out, "float32")))
+        return out
+
+    def mlp_fit_scales(self):
+        s = np.empty(MLP_SCALES, dtype=np.float32)
+        self._check(lib().ebe_mlp_fit_scales(self._h, s.ctypes.data_as(C.POINTER(C.c_float))))
+        return s
+
+    def mlp_train(self, idx, lr):
+        """Adam steps over minibatches idx (int64 CUDA tensor [steps][batch]); returns the losses."""
+        steps, batch = idx.shape
+        loss = np.empty(steps, dtype=np.float64)
+        self._check(lib().ebe_mlp_train(self._h, int(steps), int(batch), _devt(idx, "int64"), float(lr),
+                                        loss.ctypes.data_as(d_p)))
+        return loss
 
     def sizes(self):
         v = [C.c_int64() for _ in range(4)]

@@ -197,6 +197,39 @@ def random_vector(seed: int, n: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Random draws of the learned predictor (passed to the library as inputs)
+# --------------------------------------------------------------------------
+MLP_SHAPES = ((64, 15), (64,), (64, 64), (64,), (3, 64), (3,))
+
+
+def mlp_init(seed: int, gain: float = 1.0) -> np.ndarray:
+    """Glorot-uniform weights and zero biases, flattened W1, b1, W2, b2, W3, b3 (float32)."""
+    rng = np.random.default_rng([seed, 4099])
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            lim = gain * math.sqrt(6.0 / (shape[0] + shape[1]))
+            parts.append(rng.uniform(-lim, lim, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def minibatches(seed: int, steps: int, batch: int, count: int) -> np.ndarray:
+    """Sample indices [steps][batch] drawn uniformly from 0..count-1 (int64)."""
+    rng = np.random.default_rng([seed, 8191])
+    return rng.integers(0, count, size=(steps, batch), dtype=np.int64)
+
+
+def sample_nodes(seed: int, fixed: np.ndarray, k: int) -> np.ndarray:
+    """k distinct nodes with no fixed component (int32, sorted)."""
+    free = np.where(fixed.reshape(-1, 3).max(axis=1) == 0)[0]
+    rng = np.random.default_rng([seed, 131])
+    k = min(k, free.size)
+    return np.sort(rng.choice(free, size=k, replace=False)).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------
 def rayleigh_coefficients(zeta: float, f1: float, f2: float):
@@ -236,6 +269,9 @@ class Workload:
 # The small case the oracle finishes in seconds, the single-GPU headline case,
 # and the large mesh of the mixed-precision comparison (8.5M nodes, 25.6M dof).
 SMALL = Workload("box8x8x8_p2tet_fp64", cells=(8, 8, 8), nt=100, s=16)
+# learned predictor: training and test waves of the headline mesh
+LEARN_TRAIN_SEEDS = tuple(range(100, 150))
+LEARN_TEST_SEEDS = tuple(range(200, 232))
 PLAIN = Workload("box64x64x32_p2tet_fp64", cells=(64, 64, 32), nt=1000, s=32)
 LARGE = Workload("box128x128x64_p2tet", cells=(128, 128, 64), nt=300, s=32)
 WORKLOADS = {"plain": PLAIN, "large": LARGE, "small": SMALL}

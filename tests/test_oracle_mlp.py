@@ -95,9 +95,14 @@ def test_feature_layout():
     rng = np.random.default_rng(9)
     us = [rng.standard_normal(12) for _ in range(4)]
     f = rng.standard_normal(12)
-    X = mlp.features(us, f, 2.0, 4.0)
+    X = mlp.features(us, f, 2.0, 0.5, 4.0)
     assert X.shape == (4, 15)
     node = 2
     np.testing.assert_array_equal(X[node, 0:3], us[0][6:9] / 2.0)
-    np.testing.assert_array_equal(X[node, 9:12], us[3][6:9] / 2.0)
+    np.testing.assert_allclose(X[node, 3:6], (us[0][6:9] - us[1][6:9]) / 0.5, rtol=1e-15)
+    np.testing.assert_allclose(X[node, 9:12], (us[2][6:9] - us[3][6:9]) / 0.5, rtol=1e-15)
     np.testing.assert_array_equal(X[node, 12:15], f[6:9] / 4.0)
+    # the encoding is invertible: the four displacements come back
+    d = X[:, 3:12].reshape(4, 3, 3) * 0.5
+    u1 = X[:, 0:3] * 2.0
+    np.testing.assert_allclose(u1 - d[:, 0] - d[:, 1] - d[:, 2], us[3].reshape(4, 3), atol=1e-14)

@@ -90,7 +90,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.txt"))
     ap.add_argument("--patch-elems", type=int, default=256, help="elements per EBE patch (1..256)")
-    ap.add_argument("--workload", choices=["plain", "large", "learned"], default="plain")
+    ap.add_argument("--workload", choices=["plain", "large", "learned", "ensemble"], default="plain")
+    ap.add_argument("--no-graph", action="store_true", help="ensemble: enqueue PCG trips without hipGraph")
+    ap.add_argument("--no-tune", action="store_true", help="ensemble: default case tiles instead of the autotuner")
     ap.add_argument("--train-seeds", type=int, default=50, help="learned: training trajectories")
     ap.add_argument("--train-steps", type=int, default=200, help="learned: steps per training trajectory")
     ap.add_argument("--train-nodes", type=int, default=4096, help="learned: sampled nodes per training step")
@@ -119,6 +121,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "learned":
         run_learned(args)
+        return
+    if args.workload == "ensemble":
+        run_ensemble(args)
         return
     wl = inputs.WORKLOADS[args.workload]
     prec = {"fp64": ebe.PREC_FP64, "fp32": ebe.PREC_FP32, "bf16": ebe.PREC_BF16}[args.precision]
@@ -313,6 +318,102 @@ def run_learned(args):
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "bytes_per_launch": bpe * mesh.n_elems, "mean_launch_ms": ebe_ms,
                      "timed_launches": n_timed},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_ensemble(args):
+    """Batched ensemble: 64 cases on three meshes (16x16x8 x20, 32x32x16 x24,
+    48x48x24 x20 cells), seeds 1..64, 32 snapshots, all cases advanced
+    together; baseline: one case per mesh run alone on the single-case path
+    over the same steps, scaled by the case counts."""
+    import numpy as np
+    import torch
+
+    from paper_2409_20380_amd import ebe, inputs
+    nt = args.warmup + args.steps
+    dt, tol, s = inputs.PLAIN.dt, inputs.PLAIN.tol, inputs.ENSEMBLE_S
+    aR, bR = inputs.PLAIN.rayleigh
+    t0 = time.time()
+    meshes = []
+    for cells, r in inputs.ENSEMBLE:
+        wl = inputs.Workload(f"box{cells[0]}x{cells[1]}x{cells[2]}", cells=cells, nt=nt, s=s)
+        mesh, em, mat, fx, regions, _ = wl.build()
+        meshes.append((cells, r, mesh, em, mat, fx, regions))
+    C = sum(r for _, r in inputs.ENSEMBLE)
+    waves = [inputs.base_wave(1 + c, nt, dt) for c in range(C)]
+    dof_total = sum(3 * m[2].n_nodes * m[1] for m in meshes)
+    batch = ebe.Batch(dt, aR, bR, s=s, tol=tol)
+    for cells, r, mesh, em, mat, fx, regions in meshes:
+        batch.add_mesh(mesh.coords, mesh.conn, em, mat, fx, regions, r)
+    t1 = time.time()
+    batch.assemble(tune=not args.no_tune)
+    batch.use_graph(not args.no_graph, 8)
+    t_asm = time.time() - t1
+    groups = [batch.group_info(g) for g in range(len(meshes))]
+    log(f"ensemble: {C} cases, {dof_total} dof per step; inputs {t1 - t0:.1f} s, assemble+tune {t_asm:.1f} s; {groups}")
+    G = np.zeros((nt + 1, C, 3))
+    for c in range(C):
+        G[:, c, :] = waves[c]
+    iters = []
+    for it in range(1, args.warmup + 1):
+        batch.step(G[it])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = 0.0
+    for it in range(args.warmup + 1, nt + 1):
+        st = batch.step(G[it])
+        if any(x.status != 0 for x in st):
+            raise RuntimeError(f"ensemble step {it} did not converge")
+        iters.append([x.iters for x in st])
+        res = max(res, max(x.res_true for x in st))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t
+    batch.close()
+    iters = np.array(iters)
+    log(f"batched: {args.steps} steps in {elapsed:.2f} s; mean iters per case {iters.mean():.1f}")
+    # baseline: the first case of each mesh alone on the single-case path, same steps
+    seq = 0.0
+    c0 = 0
+    seq_detail = []
+    for cells, r, mesh, em, mat, fx, regions in meshes:
+        sol = ebe.Solver(dt, aR, bR, s=s, tol=tol)
+        sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
+        for it in range(1, args.warmup + 1):
+            sol.step(base_acc=waves[c0][it])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for it in range(args.warmup + 1, nt + 1):
+            sol.step(base_acc=waves[c0][it])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        sol.close()
+        seq += el * r
+        seq_detail.append({"cells": list(cells), "ms_per_step_one_case": el / args.steps * 1e3, "cases": r})
+        c0 += r
+    value = dof_total * args.steps / elapsed
+    out = {
+        "metric": "DOF*steps/s at rel. residual 1e-8",
+        "value": value,
+        "unit": "DOF*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "ensemble_64_cases_3_meshes", "meshes": [[list(c), r] for c, r in inputs.ENSEMBLE],
+                   "dof_per_step": dof_total, "snapshots": s, "tol": tol, "seeds": "1-64",
+                   "graph": not args.no_graph, "tuned": not args.no_tune, "groups": groups},
+        "cg_iters_per_step_per_case": float(iters.mean()),
+        "max_true_rel_residual": res,
+        "sequential_single_case_value": dof_total * args.steps / seq,
+        "speedup_vs_sequential": seq / elapsed,
+        "sequential_detail": seq_detail,
+        "roofline": None,
     }
     print(json.dumps(out), flush=True)
 

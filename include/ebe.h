@@ -304,6 +304,61 @@ int ebe_mlp_fit_scales(ebe_handle* h, float* scales);
  * [steps] receives each minibatch's loss, or NULL. */
 int ebe_mlp_train(ebe_handle* h, int32_t steps, int32_t batch, const int64_t* idx, float lr, double* loss);
 
+/* ---- Batched ensembles ------------------------------------------------------
+ * Many cases (each its own base acceleration) on one or more meshes,
+ * advanced one time step together: the paper's r-case element pass (Sec.
+ * 2.2, Eq. eqmebefem; Table 2) with independent CGs per case (Algorithm 1 per
+ * case: own alpha, beta, stop test and iteration count, stopped cases masked
+ * out of the shared element passes).  Every case follows the single-case
+ * step of ebe_step (right-hand side, AB4 + regional snapshot map, refine to
+ * tol, Newmark).  Each mesh added forms a group of n_cases cases; the group's
+ * element pass works on tiles of case_tile cases (1, 2, 4 or 8) with element
+ * patches of 256 / case_tile elements and `chunks` persistent workgroups per
+ * tile, chosen by timing every candidate when ebe_batch_assemble is asked to
+ * tune.  The PCG trips of all groups are enqueued in chunks that are captured
+ * once in a hipGraph and replayed (ebe_batch_use_graph).  Only FP64 and
+ * predictor kinds 0..2 are supported.  Host arrays are copied; per-case
+ * vectors are device float64 [3 N] of that case's mesh in the caller's node
+ * order. */
+typedef struct ebe_batch ebe_batch;
+
+typedef struct {
+    int32_t iters;      /* PCG trips of this case in the last step */
+    int32_t restarts;
+    int32_t status;     /* EBE_OK or EBE_NOT_CONVERGED */
+    int32_t s_eff;
+    double res0;        /* relative residual of the initial guess */
+    double res_true;    /* relative true residual at exit */
+    double bnorm;
+} ebe_batch_stats;
+
+int ebe_batch_create(const ebe_config* cfg, void* hip_stream, ebe_batch** out);
+int ebe_batch_destroy(ebe_batch* b);
+const char* ebe_batch_last_error(const ebe_batch* b);
+/* Adds a mesh (same arrays and validation as ebe_assemble) with n_cases
+ * cases; group receives its index.  Cases are numbered group by group. */
+int ebe_batch_add_mesh(ebe_batch* b, int64_t n_nodes, const double* coords, int64_t n_elems, const int32_t* conn,
+                       const int32_t* elem_mat, int32_t n_mat, const double* mat, const uint8_t* fixed,
+                       const int32_t* region_of_node, int32_t n_cases, int32_t* group);
+/* Fixes a group's case tile and workgroups per tile (used by the next
+ * ebe_batch_assemble instead of tuning). */
+int ebe_batch_set_group_config(ebe_batch* b, int32_t group, int32_t case_tile, int32_t chunks);
+/* Builds every group (tuning the groups without a fixed configuration when
+ * tune != 0), allocates the stacked state and puts every case at rest. */
+int ebe_batch_assemble(ebe_batch* b, int32_t tune);
+int ebe_batch_group_info(ebe_batch* b, int32_t group, int32_t* first_case, int32_t* n_cases, int64_t* n_nodes,
+                         int32_t* case_tile, int32_t* chunks);
+/* on = 0 enqueues the PCG trips directly; trips (even, 2..64) per chunk. */
+int ebe_batch_use_graph(ebe_batch* b, int32_t on, int32_t trips);
+int ebe_batch_reset(ebe_batch* b);
+/* q = A_bc p for every case of a group: p, q device [n_cases][3 N]. */
+int ebe_batch_apply(ebe_batch* b, int32_t group, const double* p, double* q);
+/* One time step of every case: base_acc host [n_cases][3]; stats host
+ * [n_cases] or NULL.  EBE_NOT_CONVERGED if any case hit max_iter. */
+int ebe_batch_step(ebe_batch* b, const double* base_acc, ebe_batch_stats* stats);
+int ebe_batch_get_state(ebe_batch* b, int32_t case_index, double* u, double* v, double* a);
+int ebe_batch_sizes(ebe_batch* b, int32_t* n_groups, int32_t* n_cases, int64_t* total_dof);
+
 /* The configuration in effect (defaults filled in for fields given as <= 0).
  * out: host struct written by the call.  EBE_E_INVALID_ARG if out is NULL. */
 int ebe_get_config(ebe_handle* h, ebe_config* out);

@@ -14,7 +14,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libebe.so")
-SOURCES = ["topology.cpp", "kernels.hip", "mlp.hip", "api.hip"]
+SOURCES = ["topology.cpp", "kernels.hip", "mlp.hip", "batch.hip", "api.hip", "batch_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -160,6 +160,58 @@ void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, cons
 void launch_gather3(hipStream_t s, int64_t n, const int32_t* idx, const double* in, double* out);
 void launch_zero(hipStream_t s, int64_t count, double* p);
 
+// ---- batched ensembles (batch.hip): groups of r cases on one mesh, vectors
+// stacked case-major [r][N][3], slots [r][PN][3]
+constexpr int kMaxCaseTile = 8;
+struct BEbeArgs {
+    DevPatches P;
+    int r;                       // cases in the group
+    int64_t n3;                  // 3 N: stride between the cases of a stacked vector
+    int64_t pn;                  // slots per case
+    const double *in0, *in1, *in2;   // APPLY: p; PCG: z, p_prev; RHS: u, v, a
+    double* p_cur;               // PCG
+    double* qbuf;
+    double cm, ck, c1, c2;
+    const double* g;             // RHS: base acceleration per case [r][3]
+    int mask_in;                 // APPLY
+    DevScalars* sc;              // [r]
+    const DevScalars* guard;     // APPLY: only cases with a true-residual check due
+    const double* upd_part;      // update partials [2][kResArrays][r][g_upd]
+    int g_upd;
+    double* pap_part;            // [r][chunks]
+    const int* trip;             // current trip index (device)
+    int max_iter;
+    double tol;
+};
+struct BNodeArgs {
+    DevNodes N;
+    int r;
+    int64_t pn;
+    const double* qbuf;
+    const double* b;
+    const double* p;
+    const double* binv6;
+    double *x, *r_, *z;
+    DevScalars* sc;
+    const double* pap_part;
+    int g_pap;
+    double* part;                // [2][kResArrays][r][g_upd]
+    int g_upd;                   // node-wise workgroups per case (<= 256)
+    const int* trip;
+};
+size_t bebe_lds_bytes(const DevPatches& P, int ct, int mode);
+bool bebe_set_lds_limit(const DevPatches& P, int ct);
+// mode: MODE_APPLY 0, MODE_PCG 1, MODE_RHS 2; grid (chunks, ceil(r / ct)), chunks a multiple of 8, <= 512
+void launch_bebe(hipStream_t s, int mode, const BEbeArgs& A, int ct, int chunks);
+void launch_bupdate(hipStream_t s, const BNodeArgs& A);
+void launch_bresidual(hipStream_t s, const BNodeArgs& A, int mode);
+void launch_bcheck_finalize(hipStream_t s, const BNodeArgs& A, double tol);
+// mode 0: slot sums; 1: A_bc (fixed rows take p); 2: f + slot sums, fixed rows zero
+void launch_bcombine(hipStream_t s, const BNodeArgs& A, const double* p, const double* f, double* out, int mode);
+void launch_bzero_rhs_cases(hipStream_t s, const DevScalars* sc, int r, int64_t n3, double* x);
+void launch_set_trip(hipStream_t s, int* trip, int v);
+void launch_trip_inc(hipStream_t s, int* trip);
+
 // ---- learned node-wise predictor (mlp.hip)
 constexpr int kMlpIn = 15, kMlpHid = 64, kMlpOut = 3;
 constexpr int kMlpParams = kMlpHid * kMlpIn + kMlpHid + kMlpHid * kMlpHid + kMlpHid + kMlpOut * kMlpHid + kMlpOut;

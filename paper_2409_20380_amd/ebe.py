@@ -50,13 +50,21 @@ class StepStats(C.Structure):
                 ("res0_snapshot", C.c_double), ("res0_learned", C.c_double)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("s_eff", C.c_int32),
+                ("res0", C.c_double), ("res_true", C.c_double), ("bnorm", C.c_double)]
+
+
 # Every symbol include/ebe.h declares (checked by the CPU test suite).
 EXPORTS = ("ebe_version", "ebe_create", "ebe_destroy", "ebe_last_error", "ebe_assemble", "ebe_get_regions",
            "ebe_apply", "ebe_apply_mk", "ebe_precond", "ebe_rhs", "ebe_predict", "ebe_refine", "ebe_step",
            "ebe_get_state", "ebe_set_state", "ebe_get_history", "ebe_set_history", "ebe_sync",
            "ebe_set_kernel_timing", "ebe_kernel_time", "ebe_sizes", "ebe_get_config", "ebe_set_predictor",
            "ebe_reset", "ebe_mlp_set", "ebe_mlp_get", "ebe_mlp_forward", "ebe_mlp_grad", "ebe_mlp_adam",
-           "ebe_collect", "ebe_samples", "ebe_mlp_fit_scales", "ebe_mlp_train")
+           "ebe_collect", "ebe_samples", "ebe_mlp_fit_scales", "ebe_mlp_train", "ebe_batch_create",
+           "ebe_batch_destroy", "ebe_batch_last_error", "ebe_batch_add_mesh", "ebe_batch_set_group_config",
+           "ebe_batch_assemble", "ebe_batch_group_info", "ebe_batch_use_graph", "ebe_batch_reset", "ebe_batch_apply",
+           "ebe_batch_step", "ebe_batch_get_state", "ebe_batch_sizes")
 
 _lib = None
 vp = C.c_void_p
@@ -109,10 +117,26 @@ def lib():
     L.ebe_samples.argtypes = [vp, i64_p, vp]
     L.ebe_mlp_fit_scales.argtypes = [vp, f_p]
     L.ebe_mlp_train.argtypes = [vp, C.c_int32, C.c_int32, vp, C.c_float, d_p]
+    L.ebe_batch_create.argtypes = [C.POINTER(Config), vp, C.POINTER(vp)]
+    L.ebe_batch_destroy.argtypes = [vp]
+    L.ebe_batch_last_error.argtypes = [vp]
+    L.ebe_batch_last_error.restype = C.c_char_p
+    L.ebe_batch_add_mesh.argtypes = [vp, C.c_int64, d_p, C.c_int64, i32_p, i32_p, C.c_int32, d_p, u8_p, i32_p,
+                                     C.c_int32, i32_p]
+    L.ebe_batch_set_group_config.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+    L.ebe_batch_assemble.argtypes = [vp, C.c_int32]
+    L.ebe_batch_group_info.argtypes = [vp, C.c_int32, i32_p, i32_p, i64_p, i32_p, i32_p]
+    L.ebe_batch_use_graph.argtypes = [vp, C.c_int32, C.c_int32]
+    L.ebe_batch_reset.argtypes = [vp]
+    L.ebe_batch_apply.argtypes = [vp, C.c_int32, vp, vp]
+    L.ebe_batch_step.argtypes = [vp, d_p, C.POINTER(BatchStats)]
+    L.ebe_batch_get_state.argtypes = [vp, C.c_int32, vp, vp, vp]
+    L.ebe_batch_sizes.argtypes = [vp, i32_p, i32_p, i64_p]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or C.c_int
     L.ebe_version.restype = C.c_char_p
     L.ebe_last_error.restype = C.c_char_p
+    L.ebe_batch_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -373,3 +397,106 @@ class Solver:
         v = [C.c_int64() for _ in range(4)]
         self._check(lib().ebe_sizes(self._h, *[C.byref(x) for x in v]))
         return dict(n_nodes=v[0].value, n_elems=v[1].value, n_patch_nodes=v[2].value, n_patches=v[3].value)
+
+
+class Batch:
+    """A batched ensemble: cases (each with its own base acceleration) on one
+    or more meshes, advanced one time step together."""
+
+    def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
+                 max_iter=10000, drop_tol=1e-6, region_nodes=512, stream=None):
+        import torch
+        L = lib()
+        cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol, drop_tol=drop_tol,
+                     max_iter=max_iter, s=s, predictor=predictor, region_nodes=region_nodes)
+        self.cfg = cfg
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = L.ebe_batch_create(C.byref(cfg), C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise EbeError(rc, L.ebe_batch_last_error(None).decode())
+        self._h = h
+        self.groups = []     # (n_nodes, n_cases) per group
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ebe_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow_not_converged=False):
+        if rc == OK or (allow_not_converged and rc == NOT_CONVERGED):
+            return rc
+        raise EbeError(rc, lib().ebe_batch_last_error(self._h).decode())
+
+    def add_mesh(self, coords, conn, elem_mat, mat, fixed, regions=None, n_cases=1):
+        coords, cp = _host(coords, np.float64, d_p)
+        conn, np_ = _host(conn, np.int32, i32_p)
+        elem_mat, ep = _host(elem_mat, np.int32, i32_p)
+        mat, mp = _host(mat, np.float64, d_p)
+        fixed, fp = _host(fixed, np.uint8, u8_p)
+        rp = None
+        if regions is not None:
+            regions, rp = _host(regions, np.int32, i32_p)
+        g = C.c_int32()
+        self._check(lib().ebe_batch_add_mesh(self._h, coords.shape[0], cp, conn.shape[0], np_, ep, mat.shape[0], mp,
+                                             fp, rp, int(n_cases), C.byref(g)))
+        self.groups.append((coords.shape[0], int(n_cases)))
+        return g.value
+
+    def set_group_config(self, group, case_tile, chunks):
+        self._check(lib().ebe_batch_set_group_config(self._h, int(group), int(case_tile), int(chunks)))
+
+    def assemble(self, tune=True):
+        self._check(lib().ebe_batch_assemble(self._h, 1 if tune else 0))
+
+    def group_info(self, group):
+        v = [C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32(), C.c_int32()]
+        self._check(lib().ebe_batch_group_info(self._h, int(group), *[C.byref(x) for x in v]))
+        return dict(first_case=v[0].value, n_cases=v[1].value, n_nodes=v[2].value, case_tile=v[3].value,
+                    chunks=v[4].value)
+
+    def use_graph(self, on=True, trips=8):
+        self._check(lib().ebe_batch_use_graph(self._h, 1 if on else 0, int(trips)))
+
+    def reset(self):
+        self._check(lib().ebe_batch_reset(self._h))
+
+    @property
+    def n_cases(self):
+        return sum(r for _, r in self.groups)
+
+    def apply(self, group, p):
+        import torch
+        q = torch.empty_like(p)
+        self._check(lib().ebe_batch_apply(self._h, int(group), _dev(p), _dev(q)))
+        return q
+
+    def step(self, base_acc):
+        g, gp = _host(np.asarray(base_acc, dtype=np.float64).reshape(-1, 3), np.float64, d_p)
+        if g.shape[0] != self.n_cases:
+            raise ValueError(f"need {self.n_cases} base accelerations")
+        st = (BatchStats * self.n_cases)()
+        rc = lib().ebe_batch_step(self._h, gp, st)
+        self._check(rc, allow_not_converged=True)
+        return list(st)
+
+    def get_state(self, case):
+        import torch
+        n = None
+        c = int(case)
+        for nodes, r in self.groups:
+            if c < r:
+                n = nodes
+                break
+            c -= r
+        if n is None:
+            raise ValueError("no such case")
+        u, v, a = (torch.empty(3 * n, dtype=torch.float64, device="cuda") for _ in range(3))
+        self._check(lib().ebe_batch_get_state(self._h, int(case), _dev(u), _dev(v), _dev(a)))
+        return u, v, a

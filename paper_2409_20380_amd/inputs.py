@@ -275,3 +275,6 @@ LEARN_TEST_SEEDS = tuple(range(200, 232))
 PLAIN = Workload("box64x64x32_p2tet_fp64", cells=(64, 64, 32), nt=1000, s=32)
 LARGE = Workload("box128x128x64_p2tet", cells=(128, 128, 64), nt=300, s=32)
 WORKLOADS = {"plain": PLAIN, "large": LARGE, "small": SMALL}
+# batched ensemble: (cells, cases) per mesh; cases take seeds 1..64 in order
+ENSEMBLE = (((16, 16, 8), 20), ((32, 32, 16), 24), ((48, 48, 24), 20))
+ENSEMBLE_STEPS, ENSEMBLE_S = 500, 32

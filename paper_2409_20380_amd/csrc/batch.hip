@@ -54,50 +54,80 @@ __device__ __forceinline__ double bebe_patch(const BEbeArgs& A, int patch, int c
     double* lk = lm + stride;                               // [max_pn][CT][3] (RHS)
     double* lx = lk + (MODE == MODE_RHS ? stride : 0);      // [max_nv][3]
 
-    // gather: (node, case) pairs, case fastest
-    for (int q = tid; q < npn * CT; q += NT) {
-        const int j = q / CT, kk = q % CT;
-        const uint32_t ent = P.nodes[pn0 + j];
-        const int64_t g = (int64_t)(ent & ~kOwnerBit);
-        const int c = c0 + kk;
-        const bool act = sm.active[kk];
-        double v[3] = {0.0, 0.0, 0.0};
-        if (act) {
-            const int64_t o = (int64_t)c * A.n3 + 3 * g;
-            if (MODE == MODE_APPLY) {
-                const uint8_t fm = A.mask_in ? P.fixmask[g] : 0;
+    // The element record is loaded first: its latency overlaps the gather.
+    ElemRec rec{};
+    if (e < ne) rec = P.elems[e0 + e];
+
+    // Gather: (node, case) pairs, case fastest; all loads of a group of
+    // GU x NT pairs are issued before any is consumed (a deeper group for a
+    // single-case tile, where the registers allow it).
+    constexpr int GU = CT == 1 ? 4 : 2;
+    const int npairs = npn * CT;
+    for (int qb = 0; qb < npairs; qb += NT * GU) {
+        uint32_t ent[GU];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) v[d] = (fm >> d) & 1 ? 0.0 : A.in0[o + d];
+        for (int u = 0; u < GU; ++u) {
+            const int q = qb + tid + NT * u;
+            ent[u] = q < npairs ? P.nodes[pn0 + q / CT] : 0u;
+        }
+        double v[GU][3], w[GU][3], a3[GU][3], xc[GU][3];
+        uint8_t fm[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int q = qb + tid + NT * u;
+            const int j = q / CT, kk = q % CT;
+            const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
+            const bool act = q < npairs && sm.active[kk];
+            const int64_t o = (int64_t)(c0 + kk) * A.n3 + 3 * g;
+            fm[u] = (MODE == MODE_APPLY && act && A.mask_in) ? P.fixmask[g] : 0;
+            const bool need1 = act && (MODE == MODE_RHS || (MODE == MODE_PCG && sm.beta[kk] != 0.0));
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                v[u][d] = act ? A.in0[o + d] : 0.0;
+                w[u][d] = need1 ? A.in1[o + d] : 0.0;
+                a3[u][d] = (MODE == MODE_RHS && act) ? A.in2[o + d] : 0.0;
+                xc[u][d] = (q < npairs && kk == 0 && j < nv) ? P.coords[3 * g + d] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+            const int q = qb + tid + NT * u;
+            if (q >= npairs) continue;
+            const int j = q / CT, kk = q % CT;
+            const int c = c0 + kk;
+            const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
+            const int64_t o = (int64_t)c * A.n3 + 3 * g;
+            const bool act = sm.active[kk];
+            double m[3];
+            if (MODE == MODE_APPLY) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) m[d] = (fm[u] >> d) & 1 ? 0.0 : v[u][d];
             } else if (MODE == MODE_PCG) {
                 const double b = sm.beta[kk];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) v[d] = b != 0.0 ? fma(b, A.in1[o + d], A.in0[o + d]) : A.in0[o + d];
-                if (ent & kOwnerBit) {
+                for (int d = 0; d < 3; ++d) m[d] = fma(b, w[u][d], v[u][d]);
+                if (act && (ent[u] & kOwnerBit)) {
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) A.p_cur[o + d] = v[d];
+                    for (int d = 0; d < 3; ++d) A.p_cur[o + d] = m[d];
                 }
             } else {   // RHS: mass operand a + c1 v - g, stiffness operand c2 v - u
-                const double* gc = A.g + 3 * c;
+                const double* gc = A.g + 3 * (act ? c : 0);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const double uu = A.in0[o + d], vv = A.in1[o + d], aa = A.in2[o + d];
-                    v[d] = fma(A.c1, vv, aa) - gc[d];
-                    lk[(j * CT + kk) * 3 + d] = fma(A.c2, vv, -uu);
+                    m[d] = act ? fma(A.c1, w[u][d], a3[u][d]) - gc[d] : 0.0;
+                    lk[(j * CT + kk) * 3 + d] = act ? fma(A.c2, w[u][d], -v[u][d]) : 0.0;
                 }
             }
-        } else if (MODE == MODE_RHS) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) lk[(j * CT + kk) * 3 + d] = 0.0;
-        }
+            for (int d = 0; d < 3; ++d) {
+                lm[(j * CT + kk) * 3 + d] = m[d];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            lm[(j * CT + kk) * 3 + d] = v[d];
+                for (int ww = 0; ww < kEbeWaves; ++ww) la[ww * stride + (j * CT + kk) * 3 + d] = 0.0;
+            }
+            if (kk == 0 && j < nv) {
 #pragma unroll
-            for (int w = 0; w < kEbeWaves; ++w) la[w * stride + (j * CT + kk) * 3 + d] = 0.0;
-        }
-        if (kk == 0 && j < nv) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) lx[3 * j + d] = P.coords[3 * g + d];
+                for (int d = 0; d < 3; ++d) lx[3 * j + d] = xc[u][d];
+            }
         }
     }
     __syncthreads();
@@ -105,7 +135,6 @@ __device__ __forceinline__ double bebe_patch(const BEbeArgs& A, int patch, int c
     double pap = 0.0;
     if (e < ne && sm.active[k]) {
         double* acc = la + wave * stride;
-        const ElemRec rec = P.elems[e0 + e];
         GeoT<double> G;
         tet_geo<double>(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
         const double* mp = P.mat + 3 * rec.mat;

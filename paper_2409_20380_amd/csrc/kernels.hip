@@ -69,8 +69,13 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     const S* in0 = static_cast<const S*>(A.in0);
     const S* in1 = static_cast<const S*>(A.in1);
 
-    // Gather: all loads of a group of GU x NT node entries are issued before any is consumed.
-    constexpr int GU = 2;
+    // The element record is loaded first: its latency overlaps the gather.
+    ElemRec rec{};
+    if (tid < ne) rec = P.elems[e0 + tid];
+
+    // Gather: all loads of a group of GU x NT node entries are issued before
+    // any is consumed (GU x NT covers a whole 256-element patch in one round).
+    constexpr int GU = 4;
     for (int jb = 0; jb < npn; jb += NT * GU) {
         uint32_t ent[GU];
 #pragma unroll
@@ -150,7 +155,6 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     double pap = 0.0;
     if (tid < ne) {
         double* acc = la + wave * stride;
-        const ElemRec rec = P.elems[e0 + tid];
         GeoT<T> G;
         tet_geo<T>(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
         const double* mp = P.mat + 3 * rec.mat;

@@ -5,7 +5,8 @@
 // nodes that are close in space are close in memory.
 // Element order: by the lowest internal id among the element's vertices,
 // ties broken by the Morton code of the centroid.  Consecutive runs of
-// patch_elems elements form a patch; a patch is processed by one workgroup
+// patch_elems elements form a patch (inside a patch the elements are dealt
+// round-robin to the workgroup's wavefronts); a patch is processed by one workgroup
 // (one element per thread) that stages the patch's nodes in LDS.  Each patch lists its nodes
 // (vertices first, so the geometry gather touches a prefix only).  Each
 // (patch, node) pair writes its partial result to its own slot; the slots of a
@@ -203,9 +204,19 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     std::vector<int32_t> nodes;
     std::vector<int32_t> local(N, -1);
     std::vector<uint8_t> seen(N, 0);
+    std::vector<int32_t> dealt;
     for (int64_t p = 0; p < Ppad; ++p) {
         int64_t e0 = std::min<int64_t>(p * patch_elems, E), e1 = std::min<int64_t>(e0 + patch_elems, E);
         T.patch_el_ptr[p + 1] = (int32_t)e1;
+        // Deal the patch's spatially sorted elements round-robin to the
+        // wavefronts of the workgroup: elements that share nodes (e.g. the six
+        // tetrahedra of one cell) land in different wavefronts, so the lanes
+        // of one wavefront rarely add into the same LDS address in the same
+        // instruction.
+        dealt.clear();
+        for (int w = 0; w < kDealWaves; ++w)
+            for (int64_t k = e0 + w; k < e1; k += kDealWaves) dealt.push_back(eord[k]);
+        std::copy(dealt.begin(), dealt.end(), eord.begin() + e0);
         nodes.clear();
         for (int64_t k = e0; k < e1; ++k) {
             const int32_t* c = conn + 10 * (int64_t)eord[k];

@@ -646,7 +646,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, c
     if (inner_count && blockIdx.x == 0 && threadIdx.x == 0) *inner_count += 1;
     const T alpha = (T)alpha_d;
     double v0 = 0.0, v1 = 0.0;
-    constexpr int U = 2;   // nodes per thread per trip, loads of all of them issued first
+    constexpr int U = 1;   // nodes per thread per trip (one: fewer registers, more waves in flight)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n0 < N.n; n0 += U * stride) {
         T q[U][3], rv[U][3], xv[U][3], pv[U][3], B[U][6];
@@ -1004,16 +1004,19 @@ __global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_
         const int c = sc0 + 2 * k;
         sp[k] = c < ncols ? colp[c] : nullptr;
     }
-    for (int64_t base = d0; base < d1; base += TR) {
-        const int64_t row = base + srow;
-        double v[CPT];
+    // software pipeline: the next tile's loads are in flight while this tile's MFMAs run
+    double v[CPT];
 #pragma unroll
-        for (int k = 0; k < CPT; ++k) v[k] = (sp[k] && row < d1) ? sp[k][row] : 0.0;
+    for (int k = 0; k < CPT; ++k) v[k] = (sp[k] && d0 + srow < d1) ? sp[k][d0 + srow] : 0.0;
+    for (int64_t base = d0; base < d1; base += TR) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < CPT; ++k)
             if (sp[k]) tile[(sc0 + 2 * k) * LD + srow] = v[k];
         __syncthreads();
+        const int64_t nrow = base + TR + srow;
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) v[k] = (sp[k] && nrow < d1) ? sp[k][nrow] : 0.0;
         // each wave owns 32 rows of the tile: 8 k-steps of 4 rows
 #pragma unroll
         for (int t = 0; t < TR / 16; ++t) {
@@ -1136,6 +1139,8 @@ void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions
 }
 
 // x = dab + sum_j a_j y_j on each region, y_j = W.c[j + 1] (outputs).
+// x = dab + sum_j coef_j Y_j per region.  (A fully unrolled variant with all
+// 32 column loads of a row in flight measured slower, 228 vs 195 us.)
 __global__ __launch_bounds__(256) void k_pred_apply(ColPtrs W, int s_eff, const int32_t* region_start,
                                                     const double* coef, const double* dab, double* x) {
     const int r = blockIdx.x;

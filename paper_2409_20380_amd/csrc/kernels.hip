@@ -1076,10 +1076,9 @@ __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, int s, double
     __shared__ int keep[32];
     const int r = blockIdx.x, lane = threadIdx.x;
     const double* in = gh + (int64_t)r * kGhStride;
-    for (int idx = lane; idx < s * s; idx += 64) {
-        const int i = idx / s, j = idx - i * s;
-        G[i][j] = in[i * 32 + j];
-    }
+    // lane = column index throughout: row loops, no index division
+    for (int i = 0; i < s; ++i)
+        if (lane < s) G[i][lane] = in[i * 32 + lane];
     if (lane < s) y[lane] = in[1024 + lane];
     __syncthreads();
     if (lane < s) {
@@ -1087,10 +1086,8 @@ __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, int s, double
         keep[lane] = 0;
     }
     __syncthreads();
-    for (int idx = lane; idx < s * s; idx += 64) {
-        const int i = idx / s, j = idx - i * s;
-        G[i][j] = (d[i] > 0.0 && d[j] > 0.0) ? G[i][j] / (d[i] * d[j]) : 0.0;
-    }
+    for (int i = 0; i < s; ++i)
+        if (lane < s) G[i][lane] = (d[i] > 0.0 && d[lane] > 0.0) ? G[i][lane] / (d[i] * d[lane]) : 0.0;
     if (lane < s) y[lane] = d[lane] > 0.0 ? y[lane] / d[lane] : 0.0;
     __syncthreads();
     const double drop2 = drop * drop;
@@ -1105,12 +1102,9 @@ __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, int s, double
             keep[j] = kj;
         }
         __syncthreads();
-        if (kj) {  // trailing update of the upper triangle, entries spread over the lanes
-            const int m = s - j - 1;
-            for (int idx = lane; idx < m * m; idx += 64) {
-                const int k = j + 1 + idx / m, l = j + 1 + idx % m;
-                if (l >= k) G[k][l] -= G[j][k] * G[j][l];
-            }
+        if (kj && lane > j && lane < s) {  // trailing update of the upper triangle, column = lane
+            const double gjl = G[j][lane];
+            for (int k = j + 1; k <= lane; ++k) G[k][lane] -= G[j][k] * gjl;
         }
         __syncthreads();
     }

@@ -60,7 +60,7 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 }
 
 // Storage conversions.  bf16_t holds the upper 16 bits of an IEEE binary32;
-// rounding to it is round-to-nearest-even on the dropped 16 bits.
+// rounding to it is round-to-nearest-even (the native conversion).
 template <class T, class S>
 __device__ __forceinline__ T from_storage(S v) { return (T)v; }
 template <>
@@ -71,10 +71,7 @@ template <class S, class T>
 __device__ __forceinline__ S to_storage(T v) { return (S)v; }
 template <>
 __device__ __forceinline__ bf16_t to_storage<bf16_t, float>(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_t{(uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u))};
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return bf16_t{(uint16_t)(u >> 16)};
+    return bf16_t{__builtin_bit_cast(uint16_t, (__bf16)v)};   // native round to nearest even
 }
 
 template <class T>

@@ -31,26 +31,23 @@ constexpr int oW1 = 0, oB1 = kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kH
               oB3 = oW3 + kOut * kHid;
 static_assert(oB3 + kOut == kMlpParams, "parameter layout");
 
-__device__ __forceinline__ uint16_t to_bf16(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round to nearest even: the native conversion (v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ uint16_t to_bf16(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-// GELU, tanh form: z/2 (1 + tanh(c (z + 0.044715 z^3))) = z - z / (exp(2u) + 1).
+// GELU, tanh form: z/2 (1 + tanh(c (z + 0.044715 z^3))) = z - z / (exp(2u) + 1),
+// with the hardware reciprocal (one v_rcp_f32 instead of a full division).
 constexpr float kGeluC = 0.7978845608028654f;
 __device__ __forceinline__ float gelu(float z) {
     const float u = kGeluC * fmaf(0.044715f * z, z * z, z);
     const float e = __expf(2.0f * u);
-    return z - __fdividef(z, e + 1.0f);
+    return fmaf(-z, __builtin_amdgcn_rcpf(e + 1.0f), z);
 }
 // derivative: (1 + t)/2 + z (1 - t^2) c (1 + 3 * 0.044715 z^2) / 2, t = tanh(u)
 __device__ __forceinline__ float gelu_grad(float z) {
     const float u = kGeluC * fmaf(0.044715f * z, z * z, z);
     const float e = __expf(2.0f * u);
-    const float t = 1.0f - __fdividef(2.0f, e + 1.0f);
+    const float t = fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
     const float du = kGeluC * fmaf(3.0f * 0.044715f, z * z, 1.0f);
     return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * du;
 }

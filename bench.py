@@ -431,10 +431,13 @@ def read_kv(path: str) -> dict:
 
 
 def kernel_source_sha() -> str:
+    """Fingerprint of the sources the FP64 matvec kernel is built from (its
+    code, the element operator and the patch layout)."""
     import hashlib
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2409_20380_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    for name in ("kernels.hip", "element.h", "topology.cpp"):
+        with open(os.path.join(ROOT, "paper_2409_20380_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -189,3 +189,32 @@ def test_batch_max_iter_and_errors(ms):
     b.close()
     with pytest.raises(ebe.EbeError):
         ebe.Batch(0.01, predictor=3)
+
+
+@pytest.mark.slow
+def test_full_size_batch_apply_sampled_rows(oracle_lib):
+    """Largest ensemble mesh (48x48x24 cells, 20 cases) in the bench's tuned launch configuration:
+    sampled rows of A p of several cases by the oracle's element matrices."""
+    torch = pytest.importorskip("torch")
+    from paper_2409_20380_amd import ebe
+    from tests.gpu_common import sampled_rows
+    cells, r = inputs.ENSEMBLE[2]
+    say("full-size batched apply", cells, "cases", r)
+    wl = inputs.Workload("ens_large", cells=cells, nt=2, s=inputs.ENSEMBLE_S)
+    mesh, em, mat, fx, regions, _ = wl.build()
+    aR, bR = wl.rayleigh
+    cM, cK = cm_ck(wl.dt, aR, bR)
+    b = ebe.Batch(wl.dt, aR, bR, s=wl.s, tol=wl.tol)
+    b.add_mesh(mesh.coords, mesh.conn, em, mat, fx, regions, r)
+    b.assemble(tune=True)
+    say("tuned", b.group_info(0))
+    n3 = 3 * mesh.n_nodes
+    P = np.stack([inputs.random_vector(500 + c, n3) for c in range(r)])
+    Q = to_host(b.apply(0, to_dev(P.ravel()))).reshape(r, n3)
+    rng = np.random.default_rng(1)
+    nodes = np.concatenate([rng.choice(mesh.n_nodes, 60, replace=False), [0, mesh.n_nodes - 1]])
+    for c in (0, 7, r - 1):
+        ref = sampled_rows(oracle_lib, mesh, em, mat, fx, cM, cK, P[c], nodes)
+        q = Q[c].reshape(-1, 3)
+        assert np.abs(q[nodes] - ref).max() < 1e-12 * np.abs(q).max(), c
+    b.close()

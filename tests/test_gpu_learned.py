@@ -242,3 +242,28 @@ def test_learned_steps_keep_the_better_guess_and_the_answer(small, oracle_lib):
     assert err < 1e-6
     sol.set_predictor(ebe.PRED_SNAPSHOT)
     sol.reset()
+
+
+@pytest.mark.slow
+def test_full_size_inference_sampled_rows():
+    """Headline mesh size (1,081,665 nodes), the size the kind-3 step runs the network at:
+    sampled rows of the inference kernel against the oracle."""
+    torch = pytest.importorskip("torch")
+    from paper_2409_20380_amd import ebe
+    say("full-size inference")
+    mesh = inputs.box_mesh(2, 2, 2)
+    em, mat = inputs.two_layer_materials(mesh)
+    fx = inputs.fixed_bottom(mesh)
+    sol = ebe.Solver(0.01)
+    sol.assemble(mesh.coords, mesh.conn, em, mat, fx)
+    p = bf16_params(61)
+    sol.mlp_set(p, [1.0, 1.0, 1.0, 1.0])
+    n = 1081665
+    X = torch.randn((n, 15), dtype=torch.float32, device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    Y = to_host(sol.mlp_forward(X))
+    rows = np.concatenate([np.random.default_rng(2).choice(n, 2000, replace=False), [0, n - 1]])
+    Xs = to_host(X)[rows].astype(np.float64)
+    e = nrel(Y[rows], _mimic_forward(p.astype(np.float64), Xs))
+    say(f"sampled rows: rel error vs BF16-input oracle {e:.2e}")
+    assert e < INFER_MIMIC_TOL
+    sol.close()

@@ -126,6 +126,15 @@ struct ebe_handle {
         allocs.push_back(p);
         return static_cast<X*>(p);
     }
+    // Frees one allocation made by alloc (no-op for null).
+    void release(void* p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it == allocs.end()) return;
+        if (stream) (void)hipStreamSynchronize(stream);
+        (void)hipFree(p);
+        allocs.erase(it);
+    }
     template <class X>
     X* upload(const std::vector<X>& v) {
         X* d = alloc<X>(v.size());
@@ -531,6 +540,9 @@ void need_train(ebe_handle* h, int B) {
     need_mlp(h);
     if (B > h->tr_cap) {
         MlpTrain& T = h->tr;
+        for (void* q : {(void*)T.X, (void*)T.Z1, (void*)T.H1, (void*)T.Z2, (void*)T.H2, (void*)T.dY, (void*)T.dZ1,
+                        (void*)T.dZ2, (void*)T.loss_part})
+            h->release(q);
         const size_t b = (size_t)B;
         T.X = h->alloc<float>(kMlpIn * b);
         T.Z1 = h->alloc<float>(kMlpHid * b);
@@ -1095,11 +1107,14 @@ int ebe_collect(ebe_handle* h, int64_t capacity, const int32_t* nodes, int32_t k
         need_mlp(h);
         hipStream_t s = h->stream;
         if (capacity != h->samples_cap) {
+            h->release(h->samples);
             h->samples = h->alloc<float>((size_t)capacity * kMlpSample);
             h->samples_cap = capacity;
             h->samples_n = 0;
         }
         if (k > h->coll_cap_k) {
+            h->release(h->coll_nodes);
+            h->release(h->coll_stage);
             h->coll_nodes = h->alloc<int32_t>(k);
             h->coll_stage = h->alloc<double>(3 * (size_t)k);
             h->coll_cap_k = k;
@@ -1159,6 +1174,7 @@ int ebe_mlp_train(ebe_handle* h, int32_t steps, int32_t batch, const int64_t* id
         check_launch();
         if (read_flag(h)) throw Arg{"sample index out of range"};
         if (steps > h->tr_loss_cap) {
+            h->release(h->tr_loss);
             h->tr_loss = h->alloc<double>(steps);
             h->tr_loss_cap = steps;
         }

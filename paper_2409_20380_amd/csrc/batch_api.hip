@@ -40,6 +40,17 @@ thread_local std::string g_batch_create_error;
 // Allocation list with individual release (tuning candidates are dropped).
 struct Allocs {
     std::vector<void*> v;
+    Allocs() = default;
+    Allocs(const Allocs&) = delete;
+    Allocs& operator=(const Allocs&) = delete;
+    Allocs(Allocs&& o) noexcept : v(std::move(o.v)) { o.v.clear(); }
+    Allocs& operator=(Allocs&& o) noexcept {
+        free_all();
+        v = std::move(o.v);
+        o.v.clear();
+        return *this;
+    }
+    ~Allocs() { free_all(); }
     template <class X>
     X* alloc(size_t count) {
         void* p = nullptr;

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "element.h"
 #include "kernels.h"
@@ -43,22 +44,106 @@ struct EbeArgs {
 };
 
 
+// Everything the element kernels read (topology, coordinates, materials and
+// the input vectors) is read-only for the duration of a launch: those loads go
+// through the constant address space.  Uniform ones become scalar loads
+// (scalar cache), and the compiler may move all of them across the kernel's
+// own stores, so they do not queue behind slot or direction stores in the
+// in-order vector-memory counter.
+template <class X>
+__device__ __forceinline__ X ld_ro(const X* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) X*)p;
+#else
+    return *p;   // host pass: never executed
+#endif
+}
+
+struct PatchMeta {
+    int pn0, npn, nv, e0, ne;
+};
+__device__ __forceinline__ PatchMeta patch_meta(const DevPatches& P, int patch) {
+    PatchMeta m;
+    m.pn0 = ld_ro(P.pn_ptr + patch);
+    m.npn = ld_ro(P.pn_ptr + patch + 1) - m.pn0;
+    m.nv = ld_ro(P.nv + patch);
+    m.e0 = ld_ro(P.el_ptr + patch);
+    m.ne = ld_ro(P.el_ptr + patch + 1) - m.e0;
+    return m;
+}
+
+// Per-thread index data of one patch, loaded one patch ahead by the persistent
+// matvec so that the index loads (node entries, output slots) are off the
+// critical path: only the node values are loaded after them.  (The element
+// record is loaded with its own patch's node values; holding it one patch
+// ahead costs registers the element needs.)  Lanes past the patch's end load
+// entry 0 (in bounds, also for an empty padding patch) and are masked by the
+// consumer, so nothing here waits for the loads.
+// Node entries per thread per gather round: 3 x 256 = 768 covers the patches of
+// 256 elements seen on structured tetrahedral meshes (560-630 nodes); larger
+// patches take more rounds.  (Four entries per thread would not fit beside the
+// element's registers without spilling.)
+constexpr int kGU = 3;
+struct PatchPre {
+    uint32_t ent[kGU];   // node entries of the first gather round (unmasked)
+    int32_t sl[kGU];     // output slots of the first write-out round (unmasked)
+};
+
+__device__ __forceinline__ void prefetch_gather(const DevPatches& P, int patch, PatchPre& f) {
+    constexpr int NT = 64 * kEbeWaves;
+    const int tid = threadIdx.x;
+    const PatchMeta m = patch_meta(P, patch);
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {
+        const int j = tid + NT * u;
+        f.ent[u] = ld_ro(P.nodes + (j < m.npn ? m.pn0 + j : 0));
+    }
+}
+
+__device__ __forceinline__ void prefetch_slots(const DevPatches& P, int patch, PatchPre& f) {
+    constexpr int NT = 64 * kEbeWaves;
+    const int tid = threadIdx.x;
+    const PatchMeta m = patch_meta(P, patch);
+#pragma unroll
+    for (int u = 0; u < kGU; ++u) {
+        const int j = tid + NT * u;
+        f.sl[u] = ld_ro(P.slot + (j < m.npn ? m.pn0 + j : 0));
+    }
+}
+
+__device__ __forceinline__ void patch_prefetch(const DevPatches& P, int patch, PatchPre& f) {
+    prefetch_gather(P, patch, f);
+    prefetch_slots(P, patch, f);
+}
+
+template <bool B>
+using Bool = std::integral_constant<bool, B>;
+
 // One patch on one workgroup of kEbeWaves wavefronts (one element per thread),
 // compute type T, storage type S of the PCG vectors.  The waves share the
 // gather of the patch's nodes into LDS; wave w adds its elements' results into
 // its own LDS accumulator (a single wave issues its LDS atomics in program
 // order), and the kEbeWaves accumulators are summed in a fixed order: results
-// are bitwise reproducible.  Returns this thread's share of (p, A p) (PCG).
+// are bitwise reproducible.  pf holds this patch's index data on entry and is
+// refilled for patch `next` (if >= 0) while this patch computes.
+// The gather and write-out of a patch of up to kGU x 256 nodes are one
+// straight-line round each; every global load in them is unconditional (lanes
+// past the patch's end read a valid entry, lanes past its vertices read node
+// 0's coordinates) and unused values are discarded by selects, so that the
+// compiler waits for exactly the loads it needs.  Larger patches take further
+// rounds.  Returns this thread's share of (p, A p) (PCG).
 template <int MODE, class T, class S>
-__device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double beta_d, double* lds) {
+__device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double beta_d, double* lds, PatchPre& pf,
+                                            int next) {
     const DevPatches& P = A.P;
     constexpr int NT = 64 * kEbeWaves;
+    constexpr int GU = kGU;
     const int tid = threadIdx.x, wave = tid >> 6;
-    const int pn0 = P.pn_ptr[patch], npn = P.pn_ptr[patch + 1] - pn0;
-    const int nv = P.nv[patch];
-    const int e0 = P.el_ptr[patch], ne = P.el_ptr[patch + 1] - e0;
+    const PatchMeta m = patch_meta(P, patch);
+    const int pn0 = m.pn0, npn = m.npn, nv = m.nv, e0 = m.e0, ne = m.ne;
     const int stride = 3 * P.max_pn;
     const T beta = (T)beta_d;
+    const bool use_in1 = MODE == MODE_RHS || (MODE == MODE_PCG && beta_d != 0.0);
     // The per-wave accumulators are FP64 in every variant: LDS FP32 atomic adds
     // were measured to stall the LDS queue (about 8x the issue wait of the FP64
     // ones), and FP64 accumulation is at least as accurate.
@@ -69,87 +154,98 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     const S* in0 = static_cast<const S*>(A.in0);
     const S* in1 = static_cast<const S*>(A.in1);
 
-    // The element record is loaded first: its latency overlaps the gather.
-    ElemRec rec{};
-    if (tid < ne) rec = P.elems[e0 + tid];
-
-    // Gather: all loads of a group of GU x NT node entries are issued before
-    // any is consumed (GU x NT covers a whole 256-element patch in one round).
-    constexpr int GU = 4;
-    for (int jb = 0; jb < npn; jb += NT * GU) {
+    // Gather round: all loads of GU x NT node entries are issued before any is consumed.
+    auto gather = [&](auto first, int jb) {
         uint32_t ent[GU];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int j = jb + tid + NT * u;
-            ent[u] = j < npn ? P.nodes[pn0 + j] : 0u;
+            const uint32_t e = decltype(first)::value ? pf.ent[u] : ld_ro(P.nodes + (j < npn ? pn0 + j : 0));
+            ent[u] = j < npn ? e : 0u;
         }
-        T v[GU][3], w[GU][3], xc[GU][3];
+        S v[GU][3], w[GU][3];
+        double xc[GU][3], a3[GU][3];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int j = jb + tid + NT * u;
             const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
-            const bool ok = j < npn;
+            const int64_t gx = j < nv ? g : 0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                v[u][c] = ok ? from_storage<T>(in0[3 * g + c]) : T(0);
-                w[u][c] = (ok && (MODE == MODE_RHS || (MODE == MODE_PCG && beta_d != 0.0)))
-                              ? from_storage<T>(in1[3 * g + c]) : T(0);
-                xc[u][c] = (ok && j < nv) ? (T)P.coords[3 * g + c] : T(0);
+                v[u][c] = ld_ro(in0 + 3 * g + c);
+                if (MODE != MODE_APPLY) w[u][c] = ld_ro(in1 + 3 * g + c);
+                if (MODE == MODE_RHS) a3[u][c] = ld_ro(A.in2 + 3 * g + c);
+                xc[u][c] = ld_ro(P.coords + 3 * gx + c);
             }
         }
-        T a3[GU][3];
-        if (MODE == MODE_RHS) {
-#pragma unroll
-            for (int u = 0; u < GU; ++u) {
-                const int j = jb + tid + NT * u;
-                const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) a3[u][c] = j < npn ? (T)A.in2[3 * g + c] : T(0);
-            }
-        }
+        // Consume every loaded value (LDS writes) before the direction stores
+        // are issued: the stores are conditional, and a load consumed after a
+        // conditional store would make the compiler wait for that store too.
+        S sp[GU][3];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int j = jb + tid + NT * u;
-            if (j >= npn) continue;
             const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
-            T v0 = v[u][0], v1 = v[u][1], v2 = v[u][2];
+            T v0 = from_storage<T>(v[u][0]), v1 = from_storage<T>(v[u][1]), v2 = from_storage<T>(v[u][2]);
             if (MODE == MODE_APPLY) {
                 if (A.mask_in) {
-                    uint8_t fm = P.fixmask[g];
+                    uint8_t fm = ld_ro(P.fixmask + g);
                     if (fm & 1) v0 = T(0);
                     if (fm & 2) v1 = T(0);
                     if (fm & 4) v2 = T(0);
                 }
             } else if (MODE == MODE_PCG) {
-                v0 = fma(beta, w[u][0], v0);
-                v1 = fma(beta, w[u][1], v1);
-                v2 = fma(beta, w[u][2], v2);
+                // p = z + beta p_prev; p_prev is not used on the first trip of a cycle (beta = 0)
+                const T w0 = use_in1 ? from_storage<T>(w[u][0]) : T(0);
+                const T w1 = use_in1 ? from_storage<T>(w[u][1]) : T(0);
+                const T w2 = use_in1 ? from_storage<T>(w[u][2]) : T(0);
+                v0 = fma(beta, w0, v0);
+                v1 = fma(beta, w1, v1);
+                v2 = fma(beta, w2, v2);
                 // the matvec uses p as stored, so that q = A p holds for the stored p
-                const S s0 = to_storage<S>(v0), s1 = to_storage<S>(v1), s2 = to_storage<S>(v2);
-                v0 = from_storage<T>(s0); v1 = from_storage<T>(s1); v2 = from_storage<T>(s2);
-                if (ent[u] & kOwnerBit) {
-                    S* pc = static_cast<S*>(A.p_cur);
-                    pc[3 * g] = s0; pc[3 * g + 1] = s1; pc[3 * g + 2] = s2;
-                }
-            } else {  // RHS: v = u, w = v (velocity), a3 = a
+                sp[u][0] = to_storage<S>(v0); sp[u][1] = to_storage<S>(v1); sp[u][2] = to_storage<S>(v2);
+                v0 = from_storage<T>(sp[u][0]); v1 = from_storage<T>(sp[u][1]); v2 = from_storage<T>(sp[u][2]);
+            } else if (j < npn) {  // RHS: v = u, w = v (velocity), a3 = a
                 const T u0 = v0, u1 = v1, u2 = v2;
-                v0 = fma((T)A.c1, w[u][0], a3[u][0]) - (T)A.g0;
-                v1 = fma((T)A.c1, w[u][1], a3[u][1]) - (T)A.g1;
-                v2 = fma((T)A.c1, w[u][2], a3[u][2]) - (T)A.g2;
-                lk[3 * j] = fma((T)A.c2, w[u][0], -u0);
-                lk[3 * j + 1] = fma((T)A.c2, w[u][1], -u1);
-                lk[3 * j + 2] = fma((T)A.c2, w[u][2], -u2);
+                const T w0 = from_storage<T>(w[u][0]), w1 = from_storage<T>(w[u][1]), w2 = from_storage<T>(w[u][2]);
+                v0 = fma((T)A.c1, w0, (T)a3[u][0]) - (T)A.g0;
+                v1 = fma((T)A.c1, w1, (T)a3[u][1]) - (T)A.g1;
+                v2 = fma((T)A.c1, w2, (T)a3[u][2]) - (T)A.g2;
+                lk[3 * j] = fma((T)A.c2, w0, -u0);
+                lk[3 * j + 1] = fma((T)A.c2, w1, -u1);
+                lk[3 * j + 2] = fma((T)A.c2, w2, -u2);
             }
-            lm[3 * j] = v0; lm[3 * j + 1] = v1; lm[3 * j + 2] = v2;
+            if (j < npn) {
+                lm[3 * j] = v0; lm[3 * j + 1] = v1; lm[3 * j + 2] = v2;
 #pragma unroll
-            for (int q = 0; q < kEbeWaves; ++q) {
-                la[q * stride + 3 * j] = 0.0; la[q * stride + 3 * j + 1] = 0.0; la[q * stride + 3 * j + 2] = 0.0;
+                for (int q = 0; q < kEbeWaves; ++q) {
+                    la[q * stride + 3 * j] = 0.0; la[q * stride + 3 * j + 1] = 0.0; la[q * stride + 3 * j + 2] = 0.0;
+                }
             }
             if (j < nv) {
-                lx[3 * j] = xc[u][0]; lx[3 * j + 1] = xc[u][1]; lx[3 * j + 2] = xc[u][2];
+                lx[3 * j] = (T)xc[u][0]; lx[3 * j + 1] = (T)xc[u][1]; lx[3 * j + 2] = (T)xc[u][2];
             }
         }
-    }
+        if (MODE == MODE_PCG) {
+            S* pc = static_cast<S*>(A.p_cur);
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
+                if (ent[u] & kOwnerBit) {   // entries past the patch's end are 0: no owner bit
+                    pc[3 * g] = sp[u][0]; pc[3 * g + 1] = sp[u][1]; pc[3 * g + 2] = sp[u][2];
+                }
+            }
+        }
+    };
+    // this thread's element record and material, in flight with the node values
+    const ElemRec rec = ld_ro(P.elems + (tid < ne ? e0 + tid : 0));
+    gather(Bool<true>{}, 0);
+    for (int jb = NT * GU; jb < npn; jb += NT * GU) gather(Bool<false>{}, jb);
+    const double* mp = P.mat + 3 * rec.mat;
+    const double m_lam = ld_ro(mp), m_mu = ld_ro(mp + 1), m_rho = ld_ro(mp + 2);
+    // in flight during this patch's elements; issued unconditionally (the last
+    // patch re-reads its own entries) so the compiler can count the loads in flight
+    prefetch_gather(P, next >= 0 ? next : patch, pf);
     __syncthreads();
 
     double pap = 0.0;
@@ -157,10 +253,9 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
         double* acc = la + wave * stride;
         GeoT<T> G;
         tet_geo<T>(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
-        const double* mp = P.mat + 3 * rec.mat;
         const T w = G.V * T(1.0 / 20.0) * (T)A.ck;
-        const T lamV = (T)mp[0] * w, muV = (T)mp[1] * w;
-        const T mc = (T)(A.cm * mp[2]) * G.V * T(1.0 / 420.0);
+        const T lamV = (T)m_lam * w, muV = (T)m_mu * w;
+        const T mc = (T)(A.cm * m_rho) * G.V * T(1.0 / 420.0);
         T pm[10][3], pk[10][3];
 #pragma unroll
         for (int i = 0; i < 10; ++i) {
@@ -190,17 +285,19 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
         pap = (double)papT;
     }
     __syncthreads();
+
+    // Write-out round: the kEbeWaves accumulators of each patch node, summed in
+    // a fixed order, go to the node's slot for this patch.
     T* qb = static_cast<T*>(A.qbuf);
-    for (int jb = 0; jb < npn; jb += NT * GU) {
-        int sl[GU];
+    int sl0[GU];
+#pragma unroll
+    for (int u = 0; u < GU; ++u) sl0[u] = pf.sl[u];
+    prefetch_slots(P, next >= 0 ? next : patch, pf);
+    auto write_out = [&](auto first, int jb) {
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int j = jb + tid + NT * u;
-            sl[u] = j < npn ? P.slot[pn0 + j] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < GU; ++u) {
-            const int j = jb + tid + NT * u;
+            const int sl = decltype(first)::value ? sl0[u] : ld_ro(P.slot + (j < npn ? pn0 + j : 0));
             if (j >= npn) continue;
             double q0 = la[3 * j], q1 = la[3 * j + 1], q2 = la[3 * j + 2];
 #pragma unroll
@@ -209,10 +306,12 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
                 q1 += la[q * stride + 3 * j + 1];
                 q2 += la[q * stride + 3 * j + 2];
             }
-            T* qo = qb + 3 * (int64_t)sl[u];
+            T* qo = qb + 3 * (int64_t)sl;
             qo[0] = (T)q0; qo[1] = (T)q1; qo[2] = (T)q2;
         }
-    }
+    };
+    write_out(Bool<true>{}, 0);
+    for (int jb = NT * GU; jb < npn; jb += NT * GU) write_out(Bool<false>{}, jb);
     __syncthreads();   // LDS is reused by the next patch of a persistent workgroup
     return pap;
 }
@@ -222,7 +321,9 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
     if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
     extern __shared__ double lds[];
     const int patch = xcd_remap(blockIdx.x, gridDim.x);
-    ebe_patch<MODE, double, double>(A, patch, 0.0, lds);
+    PatchPre pf;
+    patch_prefetch(A.P, patch, pf);
+    ebe_patch<MODE, double, double>(A, patch, 0.0, lds, pf, -1);
 }
 
 // FP64 sizing; it also covers the FP32 operands of the low-precision variants.
@@ -309,8 +410,12 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe_pcg(PcgEbeArgs A) {
     const int xcd = blockIdx.x & 7, k0 = blockIdx.x >> 3, per_xcd_wg = nb >> 3;
     const int chunk = A.E.P.n_patches_pad >> 3;
     double pap = 0.0;
-    for (int k = k0; k < chunk; k += per_xcd_wg)
-        pap += ebe_patch<MODE_PCG, T, S>(A.E, xcd * chunk + k, beta, lds);
+    PatchPre pf;
+    if (k0 < chunk) patch_prefetch(A.E.P, xcd * chunk + k0, pf);
+    for (int k = k0; k < chunk; k += per_xcd_wg) {
+        const int kn = k + per_xcd_wg;
+        pap += ebe_patch<MODE_PCG, T, S>(A.E, xcd * chunk + k, beta, lds, pf, kn < chunk ? xcd * chunk + kn : -1);
+    }
     pap = block_bcast_sum(pap);
     if (tid == 0) A.pap_part[blockIdx.x] = pap;
 }

@@ -655,6 +655,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->dp.n_patches_pad = T.n_patches_pad;
         h->dp.max_pn = T.max_pn;
         h->dp.max_nv = T.max_nv;
+        h->dp.n_mat = n_mat;
         h->dn.slot_ptr = h->upload(T.slot_ptr);
         if (!ebe_set_lds_limit(h->dp)) throw Arg{"an element patch needs more LDS than the device allows; lower patch_elems"};
         h->dn.fixmask = fm;

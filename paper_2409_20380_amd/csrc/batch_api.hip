@@ -191,6 +191,7 @@ void upload_topology(Group& g, Allocs& a, hipStream_t s) {
     g.dp.n_patches_pad = T.n_patches_pad;
     g.dp.max_pn = T.max_pn;
     g.dp.max_nv = T.max_nv;
+    g.dp.n_mat = (int32_t)(T.mat_lmr.size() / 3);
     g.dn.slot_ptr = up(T.slot_ptr);
     g.dn.fixmask = fm;
     g.dn.n = T.n_nodes;

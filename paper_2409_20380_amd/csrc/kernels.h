@@ -53,6 +53,7 @@ struct DevPatches {
     const uint8_t* fixmask;     // [N]
     int32_t n_patches_pad;
     int32_t max_pn, max_nv;
+    int32_t n_mat;              // materials in `mat` (the element kernels stage them in LDS)
 };
 
 struct DevNodes {

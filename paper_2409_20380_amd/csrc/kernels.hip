@@ -72,13 +72,15 @@ __device__ __forceinline__ PatchMeta patch_meta(const DevPatches& P, int patch) 
     return m;
 }
 
-// Per-thread index data of one patch, loaded one patch ahead by the persistent
-// matvec so that the index loads (node entries, output slots) are off the
-// critical path: only the node values are loaded after them.  (The element
-// record is loaded with its own patch's node values; holding it one patch
-// ahead costs registers the element needs.)  Lanes past the patch's end load
-// entry 0 (in bounds, also for an empty padding patch) and are masked by the
-// consumer, so nothing here waits for the loads.
+// Node entries of one patch, loaded one patch ahead by the persistent matvec
+// so that the index load is off the critical path: only the node values are
+// loaded after it.  (The output slots and the element record are loaded with
+// the patch's own node values: they are first used after the gather.  Slots
+// carried from one patch to the next were copied between registers at the
+// loop's back edge, which made every wave wait there for its slot stores.)
+// Lanes past the patch's end load entry 0 (in bounds, also for an empty
+// padding patch) and are masked by the consumer, so nothing here waits for
+// the loads.
 // Node entries per thread per gather round: 3 x 256 = 768 covers the patches of
 // 256 elements seen on structured tetrahedral meshes (560-630 nodes); larger
 // patches take more rounds.  (Four entries per thread would not fit beside the
@@ -86,7 +88,6 @@ __device__ __forceinline__ PatchMeta patch_meta(const DevPatches& P, int patch) 
 constexpr int kGU = 3;
 struct PatchPre {
     uint32_t ent[kGU];   // node entries of the first gather round (unmasked)
-    int32_t sl[kGU];     // output slots of the first write-out round (unmasked)
 };
 
 __device__ __forceinline__ void prefetch_gather(const DevPatches& P, int patch, PatchPre& f) {
@@ -100,20 +101,8 @@ __device__ __forceinline__ void prefetch_gather(const DevPatches& P, int patch, 
     }
 }
 
-__device__ __forceinline__ void prefetch_slots(const DevPatches& P, int patch, PatchPre& f) {
-    constexpr int NT = 64 * kEbeWaves;
-    const int tid = threadIdx.x;
-    const PatchMeta m = patch_meta(P, patch);
-#pragma unroll
-    for (int u = 0; u < kGU; ++u) {
-        const int j = tid + NT * u;
-        f.sl[u] = ld_ro(P.slot + (j < m.npn ? m.pn0 + j : 0));
-    }
-}
-
 __device__ __forceinline__ void patch_prefetch(const DevPatches& P, int patch, PatchPre& f) {
     prefetch_gather(P, patch, f);
-    prefetch_slots(P, patch, f);
 }
 
 template <bool B>
@@ -151,10 +140,14 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     T* lm = reinterpret_cast<T*>(la + kEbeWaves * stride); // [max_pn][3] mass (or shared) operand
     T* lk = lm + stride;                                   // [max_pn][3] stiffness operand (RHS)
     T* lx = lk + (MODE == MODE_RHS ? stride : 0);          // [max_nv][3] vertex coordinates
+    // [n_mat][3] material table (lambda, mu, rho), after the FP64-sized regions above
+    const double* lmat = lds + (size_t)stride * (kEbeWaves + (MODE == MODE_RHS ? 2 : 1)) + 3 * P.max_nv;
     const S* in0 = static_cast<const S*>(A.in0);
     const S* in1 = static_cast<const S*>(A.in1);
 
-    // Gather round: all loads of GU x NT node entries are issued before any is consumed.
+    // Gather round: all loads of GU x NT node entries are issued before any is
+    // consumed; the first round also issues the loads of its output slots.
+    int sl0[GU];
     auto gather = [&](auto first, int jb) {
         uint32_t ent[GU];
 #pragma unroll
@@ -176,6 +169,13 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
                 if (MODE != MODE_APPLY) w[u][c] = ld_ro(in1 + 3 * g + c);
                 if (MODE == MODE_RHS) a3[u][c] = ld_ro(A.in2 + 3 * g + c);
                 xc[u][c] = ld_ro(P.coords + 3 * gx + c);
+            }
+        }
+        if (decltype(first)::value) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int j = tid + NT * u;
+                sl0[u] = ld_ro(P.slot + (j < npn ? pn0 + j : 0));
             }
         }
         // Consume every loaded value (LDS writes) before the direction stores
@@ -241,8 +241,6 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     const ElemRec rec = ld_ro(P.elems + (tid < ne ? e0 + tid : 0));
     gather(Bool<true>{}, 0);
     for (int jb = NT * GU; jb < npn; jb += NT * GU) gather(Bool<false>{}, jb);
-    const double* mp = P.mat + 3 * rec.mat;
-    const double m_lam = ld_ro(mp), m_mu = ld_ro(mp + 1), m_rho = ld_ro(mp + 2);
     // in flight during this patch's elements; issued unconditionally (the last
     // patch re-reads its own entries) so the compiler can count the loads in flight
     prefetch_gather(P, next >= 0 ? next : patch, pf);
@@ -253,9 +251,10 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
         double* acc = la + wave * stride;
         GeoT<T> G;
         tet_geo<T>(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
+        const double* mp = lmat + 3 * rec.mat;
         const T w = G.V * T(1.0 / 20.0) * (T)A.ck;
-        const T lamV = (T)m_lam * w, muV = (T)m_mu * w;
-        const T mc = (T)(A.cm * m_rho) * G.V * T(1.0 / 420.0);
+        const T lamV = (T)mp[0] * w, muV = (T)mp[1] * w;
+        const T mc = (T)(A.cm * mp[2]) * G.V * T(1.0 / 420.0);
         T pm[10][3], pk[10][3];
 #pragma unroll
         for (int i = 0; i < 10; ++i) {
@@ -289,10 +288,6 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     // Write-out round: the kEbeWaves accumulators of each patch node, summed in
     // a fixed order, go to the node's slot for this patch.
     T* qb = static_cast<T*>(A.qbuf);
-    int sl0[GU];
-#pragma unroll
-    for (int u = 0; u < GU; ++u) sl0[u] = pf.sl[u];
-    prefetch_slots(P, next >= 0 ? next : patch, pf);
     auto write_out = [&](auto first, int jb) {
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
@@ -316,11 +311,21 @@ __device__ __forceinline__ double ebe_patch(const EbeArgs& A, int patch, double 
     return pap;
 }
 
+// Copies the material table into LDS after the patch regions (read by the
+// element phase, which follows the first gather's barrier).
+template <int MODE>
+__device__ __forceinline__ void stage_materials(const DevPatches& P, double* lds) {
+    const int stride = 3 * P.max_pn;
+    double* lmat = lds + (size_t)stride * (kEbeWaves + (MODE == MODE_RHS ? 2 : 1)) + 3 * P.max_nv;
+    for (int i = threadIdx.x; i < 3 * P.n_mat; i += 64 * kEbeWaves) lmat[i] = ld_ro(P.mat + i);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
     if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
     extern __shared__ double lds[];
     const int patch = xcd_remap(blockIdx.x, gridDim.x);
+    stage_materials<MODE>(A.P, lds);
     PatchPre pf;
     patch_prefetch(A.P, patch, pf);
     ebe_patch<MODE, double, double>(A, patch, 0.0, lds, pf, -1);
@@ -328,7 +333,8 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
 
 // FP64 sizing; it also covers the FP32 operands of the low-precision variants.
 size_t ebe_lds_bytes(const DevPatches& P, int mode) {
-    return sizeof(double) * (size_t)(3 * P.max_pn * ((mode == MODE_RHS ? 2 : 1) + kEbeWaves) + 3 * P.max_nv);
+    return sizeof(double) *
+           (size_t)(3 * P.max_pn * ((mode == MODE_RHS ? 2 : 1) + kEbeWaves) + 3 * P.max_nv + 3 * P.n_mat);
 }
 
 // ---------------------------------------------------------------------------
@@ -410,6 +416,7 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe_pcg(PcgEbeArgs A) {
     const int xcd = blockIdx.x & 7, k0 = blockIdx.x >> 3, per_xcd_wg = nb >> 3;
     const int chunk = A.E.P.n_patches_pad >> 3;
     double pap = 0.0;
+    stage_materials<MODE_PCG>(A.E.P, lds);
     PatchPre pf;
     if (k0 < chunk) patch_prefetch(A.E.P, xcd * chunk + k0, pf);
     for (int k = k0; k < chunk; k += per_xcd_wg) {

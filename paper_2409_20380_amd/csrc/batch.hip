@@ -37,38 +37,74 @@ struct BSmem {
     double red[kEbeWaves][kMaxCaseTile];
 };
 
+// Entries per thread per gather round: a deeper round for a single-case tile,
+// where the registers allow it (3 x 256 pairs cover a 256-element patch of a
+// structured mesh); the largest depth at which each case tile does not spill.
+template <int CT>
+constexpr int bgu() { return CT == 1 ? 3 : (CT == 2 ? 1 : 2); }
+
+// Node entries of the first gather round of one patch, loaded one patch ahead
+// (pair q = node q / CT, case q % CT).  Lanes past the patch's end load entry 0
+// (in bounds) and are masked by the consumer.  Only the single-case tile
+// prefetches: with CT > 1 the entries held through the element phase make the
+// kernel spill, and the first round loads its entries itself.
+template <int CT>
+constexpr bool bprefetching() { return CT == 1; }
+template <int CT>
+struct BPre {
+    uint32_t ent[bgu<CT>()];
+};
+template <int CT>
+__device__ __forceinline__ void bprefetch(const DevPatches& P, int patch, BPre<CT>& f) {
+    if (!bprefetching<CT>()) return;
+    constexpr int NT = 64 * kEbeWaves;
+    const PatchMeta m = patch_meta(P, patch);
+    const int npairs = m.npn * CT;
+#pragma unroll
+    for (int u = 0; u < bgu<CT>(); ++u) {
+        const int q = threadIdx.x + NT * u;
+        f.ent[u] = ld_ro(P.nodes + (q < npairs ? m.pn0 + q / CT : 0));
+    }
+}
+
 // One patch for CT cases.  Thread tid handles element tid / CT of the patch
-// and case tid % CT of the tile.  Returns this thread's share of (p, A p).
+// and case tid % CT of the tile.  pf holds this patch's first-round node
+// entries and is refilled for patch `next` (if >= 0) while this patch computes.
+// As in the single-case kernel, every global load of the gather is
+// unconditional (inactive cases and cases past the group read case c0's
+// values, lanes past the patch's end read entry 0) and unused values are
+// discarded by selects, and the direction stores follow the LDS writes, so
+// the compiler waits only for the loads it needs.  (Unlike the single-case
+// kernel, the slots are loaded at the write-out: holding them through the
+// element phase makes the case-tiled kernels spill.)  Returns this thread's
+// share of (p, A p).
 template <int MODE, int CT>
-__device__ __forceinline__ double bebe_patch(const BEbeArgs& A, int patch, int c0, BSmem& sm, double* lds) {
+__device__ __forceinline__ double bebe_patch(const BEbeArgs& A, int patch, int c0, BSmem& sm, double* lds,
+                                             BPre<CT>& pf, int next) {
     const DevPatches& P = A.P;
     constexpr int NT = 64 * kEbeWaves;
+    constexpr int GU = bgu<CT>();
     const int tid = threadIdx.x, wave = tid >> 6;
     const int e = tid / CT, k = tid % CT;
-    const int pn0 = P.pn_ptr[patch], npn = P.pn_ptr[patch + 1] - pn0;
-    const int nv = P.nv[patch];
-    const int e0 = P.el_ptr[patch], ne = P.el_ptr[patch + 1] - e0;
+    const PatchMeta pm_ = patch_meta(P, patch);
+    const int pn0 = pm_.pn0, npn = pm_.npn, nv = pm_.nv, e0 = pm_.e0, ne = pm_.ne;
     const int stride = 3 * CT * P.max_pn;
     double* la = lds;                                       // kEbeWaves x [max_pn][CT][3]
     double* lm = la + kEbeWaves * stride;                   // [max_pn][CT][3]
     double* lk = lm + stride;                               // [max_pn][CT][3] (RHS)
     double* lx = lk + (MODE == MODE_RHS ? stride : 0);      // [max_nv][3]
-
-    // The element record is loaded first: its latency overlaps the gather.
-    ElemRec rec{};
-    if (e < ne) rec = P.elems[e0 + e];
-
-    // Gather: (node, case) pairs, case fastest; all loads of a group of
-    // GU x NT pairs are issued before any is consumed (a deeper group for a
-    // single-case tile, where the registers allow it).
-    constexpr int GU = CT == 1 ? 4 : 2;
+    const double* lmat = lx + 3 * P.max_nv;                 // [n_mat][3]
     const int npairs = npn * CT;
-    for (int qb = 0; qb < npairs; qb += NT * GU) {
+
+    // Gather round over (node, case) pairs, case fastest.
+    auto gather = [&](auto first, int qb) {
         uint32_t ent[GU];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int q = qb + tid + NT * u;
-            ent[u] = q < npairs ? P.nodes[pn0 + q / CT] : 0u;
+            const uint32_t en = (decltype(first)::value && bprefetching<CT>()) ? pf.ent[u]
+                                                                                : ld_ro(P.nodes + (q < npairs ? pn0 + q / CT : 0));
+            ent[u] = q < npairs ? en : 0u;
         }
         double v[GU][3], w[GU][3], a3[GU][3], xc[GU][3];
         uint8_t fm[GU];
@@ -77,59 +113,78 @@ __device__ __forceinline__ double bebe_patch(const BEbeArgs& A, int patch, int c
             const int q = qb + tid + NT * u;
             const int j = q / CT, kk = q % CT;
             const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
-            const bool act = q < npairs && sm.active[kk];
-            const int64_t o = (int64_t)(c0 + kk) * A.n3 + 3 * g;
-            fm[u] = (MODE == MODE_APPLY && act && A.mask_in) ? P.fixmask[g] : 0;
-            const bool need1 = act && (MODE == MODE_RHS || (MODE == MODE_PCG && sm.beta[kk] != 0.0));
+            const int cc = c0 + kk < A.r ? c0 + kk : c0;      // a case of the group (c0 < r)
+            const int64_t o = (int64_t)cc * A.n3 + 3 * g;
+            const int64_t gx = (kk == 0 && j < nv) ? g : 0;
+            if (MODE == MODE_APPLY) fm[u] = ld_ro(P.fixmask + g);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                v[u][d] = act ? A.in0[o + d] : 0.0;
-                w[u][d] = need1 ? A.in1[o + d] : 0.0;
-                a3[u][d] = (MODE == MODE_RHS && act) ? A.in2[o + d] : 0.0;
-                xc[u][d] = (q < npairs && kk == 0 && j < nv) ? P.coords[3 * g + d] : 0.0;
+                v[u][d] = ld_ro(A.in0 + o + d);
+                if (MODE != MODE_APPLY) w[u][d] = ld_ro(A.in1 + o + d);
+                if (MODE == MODE_RHS) a3[u][d] = ld_ro(A.in2 + o + d);
+                xc[u][d] = ld_ro(P.coords + 3 * gx + d);
             }
         }
+        double mo[GU][3];
 #pragma unroll
         for (int u = 0; u < GU; ++u) {
             const int q = qb + tid + NT * u;
-            if (q >= npairs) continue;
             const int j = q / CT, kk = q % CT;
-            const int c = c0 + kk;
-            const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
-            const int64_t o = (int64_t)c * A.n3 + 3 * g;
-            const bool act = sm.active[kk];
+            const bool act = sm.active[kk] != 0;
             double m[3];
             if (MODE == MODE_APPLY) {
+                const bool mask = A.mask_in != 0;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) m[d] = (fm[u] >> d) & 1 ? 0.0 : v[u][d];
+                for (int d = 0; d < 3; ++d) m[d] = (!act || (mask && ((fm[u] >> d) & 1))) ? 0.0 : v[u][d];
             } else if (MODE == MODE_PCG) {
                 const double b = sm.beta[kk];
 #pragma unroll
-                for (int d = 0; d < 3; ++d) m[d] = fma(b, w[u][d], v[u][d]);
-                if (act && (ent[u] & kOwnerBit)) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) A.p_cur[o + d] = m[d];
+                for (int d = 0; d < 3; ++d) {
+                    // p_prev is not used on the first trip of a cycle (beta = 0) nor for a stopped case
+                    const double wv = (act && b != 0.0) ? w[u][d] : 0.0;
+                    m[d] = act ? fma(b, wv, v[u][d]) : 0.0;
                 }
             } else {   // RHS: mass operand a + c1 v - g, stiffness operand c2 v - u
-                const double* gc = A.g + 3 * (act ? c : 0);
+                const double* gc = A.g + 3 * (act ? c0 + kk : 0);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     m[d] = act ? fma(A.c1, w[u][d], a3[u][d]) - gc[d] : 0.0;
-                    lk[(j * CT + kk) * 3 + d] = act ? fma(A.c2, w[u][d], -v[u][d]) : 0.0;
+                    if (q < npairs) lk[(j * CT + kk) * 3 + d] = act ? fma(A.c2, w[u][d], -v[u][d]) : 0.0;
                 }
             }
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                lm[(j * CT + kk) * 3 + d] = m[d];
+            for (int d = 0; d < 3; ++d) mo[u][d] = m[d];
+            if (q < npairs) {
 #pragma unroll
-                for (int ww = 0; ww < kEbeWaves; ++ww) la[ww * stride + (j * CT + kk) * 3 + d] = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    lm[(j * CT + kk) * 3 + d] = m[d];
+#pragma unroll
+                    for (int ww = 0; ww < kEbeWaves; ++ww) la[ww * stride + (j * CT + kk) * 3 + d] = 0.0;
+                }
             }
             if (kk == 0 && j < nv) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) lx[3 * j + d] = xc[u][d];
             }
         }
-    }
+        if (MODE == MODE_PCG) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int q = qb + tid + NT * u;
+                const int kk = q % CT;
+                const int64_t g = (int64_t)(ent[u] & ~kOwnerBit);
+                if (sm.active[kk] && (ent[u] & kOwnerBit)) {   // entries past the end are 0: no owner bit
+                    double* pc = A.p_cur + (int64_t)(c0 + kk) * A.n3 + 3 * g;
+                    pc[0] = mo[u][0]; pc[1] = mo[u][1]; pc[2] = mo[u][2];
+                }
+            }
+        }
+    };
+    // this thread's element record, in flight with the node values
+    const ElemRec rec = ld_ro(P.elems + (e < ne ? e0 + e : 0));
+    gather(Bool<true>{}, 0);
+    for (int qb = NT * GU; qb < npairs; qb += NT * GU) gather(Bool<false>{}, qb);
+    bprefetch<CT>(P, next >= 0 ? next : patch, pf);   // in flight during this patch's elements
     __syncthreads();
 
     double pap = 0.0;
@@ -137,7 +192,7 @@ __device__ __forceinline__ double bebe_patch(const BEbeArgs& A, int patch, int c
         double* acc = la + wave * stride;
         GeoT<double> G;
         tet_geo<double>(lx + 3 * rec.lid[0], lx + 3 * rec.lid[1], lx + 3 * rec.lid[2], lx + 3 * rec.lid[3], G);
-        const double* mp = P.mat + 3 * rec.mat;
+        const double* mp = lmat + 3 * rec.mat;
         const double w = G.V * (1.0 / 20.0) * A.ck;
         const double lamV = mp[0] * w, muV = mp[1] * w;
         const double mc = (A.cm * mp[2]) * G.V * (1.0 / 420.0);
@@ -169,21 +224,41 @@ __device__ __forceinline__ double bebe_patch(const BEbeArgs& A, int patch, int c
         }
     }
     __syncthreads();
-    for (int q = tid; q < npn * CT; q += NT) {
+    // Write-out: the kEbeWaves accumulators of each (node, case) pair, summed in
+    // a fixed order, go to the pair's slot.
+    auto write_out = [&](int qb, int sli) {
+        const int q = qb + tid;
         const int j = q / CT, kk = q % CT;
-        const int64_t sl = (int64_t)(c0 + kk) * A.pn + P.slot[pn0 + j];
-        double s[3];
+        if (q >= npairs) return;
+        double s3[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             double t = la[(j * CT + kk) * 3 + d];
 #pragma unroll
-            for (int w = 1; w < kEbeWaves; ++w) t += la[w * stride + (j * CT + kk) * 3 + d];
-            s[d] = t;
+            for (int ww = 1; ww < kEbeWaves; ++ww) t += la[ww * stride + (j * CT + kk) * 3 + d];
+            s3[d] = t;
         }
         if (sm.active[kk]) {
-            double* qo = A.qbuf + 3 * sl;
-            qo[0] = s[0]; qo[1] = s[1]; qo[2] = s[2];
+            double* qo = A.qbuf + 3 * ((int64_t)(c0 + kk) * A.pn + sli);
+            qo[0] = s3[0]; qo[1] = s3[1]; qo[2] = s3[2];
         }
+    };
+    if constexpr (CT == 1) {
+        // slots of a group of GU rounds are loaded before any is used (entry 0 past the end)
+        for (int qb = 0; qb < npairs; qb += NT * GU) {
+            int sl[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int q = qb + NT * u + tid;
+                sl[u] = ld_ro(P.slot + (q < npairs ? pn0 + q : 0));
+            }
+#pragma unroll
+            for (int u = 0; u < GU; ++u) write_out(qb + NT * u, sl[u]);
+        }
+    } else {
+        // (grouping the slot loads makes the case-tiled kernels spill)
+        for (int qb = 0; qb < npairs; qb += NT)
+            write_out(qb, ld_ro(P.slot + (qb + tid < npairs ? pn0 + (qb + tid) / CT : 0)));
     }
     __syncthreads();
     return pap;
@@ -274,8 +349,16 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_bebe(BEbeArgs A) {
     const int xcd = blockIdx.x & 7, k0 = blockIdx.x >> 3, per_xcd = nb >> 3;
     const int chunk = A.P.n_patches_pad >> 3;
     double pap_acc = 0.0;
+    {
+        const int stride = 3 * CT * A.P.max_pn;
+        stage_material_table(A.P, lds + (size_t)stride * (kEbeWaves + (MODE == MODE_RHS ? 2 : 1)) + 3 * A.P.max_nv,
+                             64 * kEbeWaves);
+    }
+    BPre<CT> pf;
+    if (k0 < chunk) bprefetch<CT>(A.P, xcd * chunk + k0, pf);
     for (int kq = k0; kq < chunk; kq += per_xcd) {
-        const double pap = bebe_patch<MODE, CT>(A, xcd * chunk + kq, c0, sm, lds);
+        const int kn = kq + per_xcd;
+        const double pap = bebe_patch<MODE, CT>(A, xcd * chunk + kq, c0, sm, lds, pf, kn < chunk ? xcd * chunk + kn : -1);
         if (MODE == MODE_PCG) {
             const double ws = case_wave_sum<CT>(pap);
             if ((tid & 63) < CT) sm.red[tid >> 6][tid & 63] = ws;
@@ -490,7 +573,8 @@ const void* bebe_fn(int ct) {
 }  // namespace
 
 size_t bebe_lds_bytes(const DevPatches& P, int ct, int mode) {
-    return sizeof(double) * ((size_t)3 * ct * P.max_pn * (kEbeWaves + (mode == MODE_RHS ? 2 : 1)) + 3 * P.max_nv);
+    return sizeof(double) *
+           ((size_t)3 * ct * P.max_pn * (kEbeWaves + (mode == MODE_RHS ? 2 : 1)) + 3 * P.max_nv + 3 * P.n_mat);
 }
 
 bool bebe_set_lds_limit(const DevPatches& P, int ct) {

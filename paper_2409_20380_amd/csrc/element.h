@@ -16,6 +16,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace ebe {
@@ -53,6 +55,42 @@ __device__ __forceinline__ double lane_partials(const double* __restrict__ p, in
 #pragma unroll
     for (int k = 0; k < PER; ++k) s += v[k];
     return s;
+}
+
+// Everything the element kernels read (topology, coordinates, materials and
+// the input vectors) is read-only for the duration of a launch: those loads go
+// through the constant address space.  Uniform ones become scalar loads
+// (scalar cache), and the compiler may move all of them across the kernel's
+// own stores, so they do not queue behind slot or direction stores in the
+// in-order vector-memory counter.
+template <class X>
+__device__ __forceinline__ X ld_ro(const X* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return *(const __attribute__((address_space(4))) X*)p;
+#else
+    return *p;   // host pass: never executed
+#endif
+}
+
+struct PatchMeta {
+    int pn0, npn, nv, e0, ne;
+};
+__device__ __forceinline__ PatchMeta patch_meta(const DevPatches& P, int patch) {
+    PatchMeta m;
+    m.pn0 = ld_ro(P.pn_ptr + patch);
+    m.npn = ld_ro(P.pn_ptr + patch + 1) - m.pn0;
+    m.nv = ld_ro(P.nv + patch);
+    m.e0 = ld_ro(P.el_ptr + patch);
+    m.ne = ld_ro(P.el_ptr + patch + 1) - m.e0;
+    return m;
+}
+
+template <bool B>
+using Bool = std::integral_constant<bool, B>;
+
+// Copies the material table (lambda, mu, rho per material) into LDS at lmat.
+__device__ __forceinline__ void stage_material_table(const DevPatches& P, double* lmat, int nthreads) {
+    for (int i = threadIdx.x; i < 3 * P.n_mat; i += nthreads) lmat[i] = ld_ro(P.mat + i);
 }
 
 __device__ __forceinline__ void lds_add(double* p, double v) {

@@ -15,7 +15,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
-#include <type_traits>
 
 #include "element.h"
 #include "kernels.h"
@@ -43,34 +42,6 @@ struct EbeArgs {
     const DevScalars* guard;  // APPLY: run only when a true-residual check is due
 };
 
-
-// Everything the element kernels read (topology, coordinates, materials and
-// the input vectors) is read-only for the duration of a launch: those loads go
-// through the constant address space.  Uniform ones become scalar loads
-// (scalar cache), and the compiler may move all of them across the kernel's
-// own stores, so they do not queue behind slot or direction stores in the
-// in-order vector-memory counter.
-template <class X>
-__device__ __forceinline__ X ld_ro(const X* p) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return *(const __attribute__((address_space(4))) X*)p;
-#else
-    return *p;   // host pass: never executed
-#endif
-}
-
-struct PatchMeta {
-    int pn0, npn, nv, e0, ne;
-};
-__device__ __forceinline__ PatchMeta patch_meta(const DevPatches& P, int patch) {
-    PatchMeta m;
-    m.pn0 = ld_ro(P.pn_ptr + patch);
-    m.npn = ld_ro(P.pn_ptr + patch + 1) - m.pn0;
-    m.nv = ld_ro(P.nv + patch);
-    m.e0 = ld_ro(P.el_ptr + patch);
-    m.ne = ld_ro(P.el_ptr + patch + 1) - m.e0;
-    return m;
-}
 
 // Node entries of one patch, loaded one patch ahead by the persistent matvec
 // so that the index load is off the critical path: only the node values are
@@ -104,9 +75,6 @@ __device__ __forceinline__ void prefetch_gather(const DevPatches& P, int patch, 
 __device__ __forceinline__ void patch_prefetch(const DevPatches& P, int patch, PatchPre& f) {
     prefetch_gather(P, patch, f);
 }
-
-template <bool B>
-using Bool = std::integral_constant<bool, B>;
 
 // One patch on one workgroup of kEbeWaves wavefronts (one element per thread),
 // compute type T, storage type S of the PCG vectors.  The waves share the
@@ -317,7 +285,7 @@ template <int MODE>
 __device__ __forceinline__ void stage_materials(const DevPatches& P, double* lds) {
     const int stride = 3 * P.max_pn;
     double* lmat = lds + (size_t)stride * (kEbeWaves + (MODE == MODE_RHS ? 2 : 1)) + 3 * P.max_nv;
-    for (int i = threadIdx.x; i < 3 * P.n_mat; i += 64 * kEbeWaves) lmat[i] = ld_ro(P.mat + i);
+    stage_material_table(P, lmat, 64 * kEbeWaves);
 }
 
 template <int MODE>

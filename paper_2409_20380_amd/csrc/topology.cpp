@@ -6,7 +6,8 @@
 // Element order: by the lowest internal id among the element's vertices,
 // ties broken by the Morton code of the centroid.  Consecutive runs of
 // patch_elems elements form a patch (inside a patch the elements are dealt
-// round-robin to the workgroup's wavefronts); a patch is processed by one workgroup
+// round-robin to the workgroup's groups of 8 lanes and the local node ids are
+// spread over the LDS banks, see spread_banks); a patch is processed by one workgroup
 // (one element per thread) that stages the patch's nodes in LDS.  Each patch lists its nodes
 // (vertices first, so the geometry gather touches a prefix only).  Each
 // (patch, node) pair writes its partial result to its own slot; the slots of a
@@ -15,6 +16,7 @@
 #include "topology.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <numeric>
@@ -48,6 +50,107 @@ struct Box {
     }
 };
 }  // namespace
+
+// Patch-local numbering against LDS bank conflicts.  The element kernels add
+// each element's nodal results into a per-wavefront FP64 LDS accumulator
+// indexed by the patch-local node id l (doubles 3l .. 3l+2); the same ids index
+// the element's reads of the staged operand.  On gfx950 an FP64 LDS atomic is
+// serviced in groups of 8 lanes over 16 bank pairs (32 four-byte banks),
+// measured: lanes of one group whose doubles fall on the same bank pair are
+// serialised, so the cost of one atomic instruction of one group is the
+// largest number of its lanes that share a bank pair.  Double 3l + c lies on
+// bank pair (3l + c) mod 16, and 3 is invertible mod 16, so the lanes of a
+// group conflict exactly when their node ids agree mod 16.
+//
+// spread_banks() reassigns the local ids of one patch so that, for every group
+// of 8 consecutive elements (the 8 lanes) and every element position i
+// (the i-th node of each element, added by the same instruction), the ids are
+// spread over the residues mod 16.  Ids are only exchanged between nodes of the
+// same kind (vertex or edge node: vertices keep the prefix [0, nv)) inside an
+// aligned block of 64 ids -- the ids one wavefront gathers and writes out in
+// one instruction -- so the set of global addresses each gather and write-out
+// instruction touches is unchanged.  Greedy exchanges that lower the number of
+// same-residue pairs, over a few passes; deterministic.
+constexpr int kLdsLaneGroup = 8;    // lanes serviced together by an FP64 LDS atomic
+constexpr int kLdsBankPairs = 16;   // 8-byte bank pairs
+
+static void spread_banks(int ne, const std::vector<std::array<int32_t, 10>>& el_local, int nv, int npn,
+                         std::vector<int32_t>& newid) {
+    // sets: (lane group, position); members: local node ids (pre-renumbering)
+    const int ngroups = (ne + kLdsLaneGroup - 1) / kLdsLaneGroup;
+    const int nsets = ngroups * 10;
+    std::vector<std::vector<int32_t>> memb(npn);   // sets containing each node (with multiplicity)
+    for (int e = 0; e < ne; ++e)
+        for (int i = 0; i < 10; ++i) memb[el_local[e][i]].push_back((e / kLdsLaneGroup) * 10 + i);
+    newid.resize(npn);
+    std::iota(newid.begin(), newid.end(), 0);
+    std::vector<int32_t> at(npn);                  // node at each id
+    std::iota(at.begin(), at.end(), 0);
+    std::vector<int32_t> cnt((size_t)nsets * kLdsBankPairs, 0);
+    auto res = [&](int node) { return newid[node] % kLdsBankPairs; };
+    for (int v = 0; v < npn; ++v)
+        for (int s : memb[v]) cnt[(size_t)s * kLdsBankPairs + res(v)]++;
+    // change of the number of same-residue pairs if node v moves from residue a to b
+    auto move_delta = [&](int v, int a, int b) {
+        if (a == b) return 0;
+        int d = 0;
+        for (int s : memb[v]) {
+            const int32_t* c = &cnt[(size_t)s * kLdsBankPairs];
+            d += c[b] - (c[a] - 1);
+        }
+        return d;
+    };
+    auto apply_move = [&](int v, int a, int b) {
+        for (int s : memb[v]) {
+            cnt[(size_t)s * kLdsBankPairs + a]--;
+            cnt[(size_t)s * kLdsBankPairs + b]++;
+        }
+    };
+    int dv[kLdsBankPairs];
+    for (int pass = 0; pass < 4; ++pass) {
+        bool changed = false;
+        for (int v = 0; v < npn; ++v) {
+            const int idv = newid[v], ra = idv % kLdsBankPairs;
+            // only nodes in a conflicting set, and only residues that help v
+            int worst = 0;
+            for (int s : memb[v]) worst = std::max(worst, cnt[(size_t)s * kLdsBankPairs + ra]);
+            if (worst <= 1) continue;
+            bool any = false;
+            for (int r = 0; r < kLdsBankPairs; ++r) {
+                dv[r] = move_delta(v, ra, r);
+                any = any || dv[r] < 0;
+            }
+            if (!any) continue;
+            // ids v may take: same 64-block, same kind
+            const int blk0 = idv / 64 * 64, blk1 = std::min(npn, blk0 + 64);
+            const int lo = idv < nv ? blk0 : std::max(blk0, nv), hi = idv < nv ? std::min(blk1, nv) : blk1;
+            int best = 0, best_id = -1;
+            for (int idu = lo; idu < hi; ++idu) {
+                const int rb = idu % kLdsBankPairs;
+                if (rb == ra || dv[rb] >= 0) continue;
+                const int u = at[idu];
+                // exchange v (ra -> rb) and u (rb -> ra); sets holding both see both moves
+                apply_move(v, ra, rb);
+                const int d = dv[rb] + move_delta(u, rb, ra);
+                apply_move(v, rb, ra);
+                if (d < best) {
+                    best = d;
+                    best_id = idu;
+                }
+            }
+            if (best_id >= 0) {
+                const int u = at[best_id], rb = best_id % kLdsBankPairs;
+                apply_move(v, ra, rb);
+                apply_move(u, rb, ra);
+                std::swap(newid[v], newid[u]);
+                at[newid[v]] = v;
+                at[newid[u]] = u;
+                changed = true;
+            }
+        }
+        if (!changed) break;
+    }
+}
 
 static char g_buf[512];
 template <class... A>
@@ -204,18 +307,21 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     std::vector<int32_t> nodes;
     std::vector<int32_t> local(N, -1);
     std::vector<uint8_t> seen(N, 0);
-    std::vector<int32_t> dealt;
+    std::vector<int32_t> dealt, newid, ordered;
+    std::vector<std::array<int32_t, 10>> el_local;
     for (int64_t p = 0; p < Ppad; ++p) {
         int64_t e0 = std::min<int64_t>(p * patch_elems, E), e1 = std::min<int64_t>(e0 + patch_elems, E);
         T.patch_el_ptr[p + 1] = (int32_t)e1;
         // Deal the patch's spatially sorted elements round-robin to the
-        // wavefronts of the workgroup: elements that share nodes (e.g. the six
-        // tetrahedra of one cell) land in different wavefronts, so the lanes
-        // of one wavefront rarely add into the same LDS address in the same
-        // instruction.
+        // groups of 8 lanes (kLdsLaneGroup) of the workgroup: elements that
+        // share nodes (e.g. the six tetrahedra of one cell, which share the
+        // cell's diagonal at the same element positions) land in different
+        // lane groups, so the lanes serviced together by one LDS atomic rarely
+        // add into the same address.
+        const int deal = std::max(1, patch_elems / kLdsLaneGroup);
         dealt.clear();
-        for (int w = 0; w < kDealWaves; ++w)
-            for (int64_t k = e0 + w; k < e1; k += kDealWaves) dealt.push_back(eord[k]);
+        for (int w = 0; w < deal; ++w)
+            for (int64_t k = e0 + w; k < e1; k += deal) dealt.push_back(eord[k]);
         std::copy(dealt.begin(), dealt.end(), eord.begin() + e0);
         nodes.clear();
         for (int64_t k = e0; k < e1; ++k) {
@@ -229,6 +335,17 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
         int nv = 0;
         for (int32_t v : nodes) nv += role[T.i2u[v]] == 1;
         if (nodes.size() > 65535) return "patch too large";
+        for (size_t j = 0; j < nodes.size(); ++j) local[nodes[j]] = (int32_t)j;
+        // spread the local ids over the LDS bank pairs (see spread_banks)
+        el_local.resize(e1 - e0);
+        for (int64_t k = e0; k < e1; ++k) {
+            const int32_t* c = conn + 10 * (int64_t)eord[k];
+            for (int i = 0; i < 10; ++i) el_local[k - e0][i] = local[T.u2i[c[i]]];
+        }
+        spread_banks((int)(e1 - e0), el_local, nv, (int)nodes.size(), newid);
+        ordered.assign(nodes.size(), 0);
+        for (size_t j = 0; j < nodes.size(); ++j) ordered[newid[j]] = nodes[j];
+        nodes.swap(ordered);
         for (size_t j = 0; j < nodes.size(); ++j) {
             int32_t v = nodes[j];
             local[v] = (int32_t)j;

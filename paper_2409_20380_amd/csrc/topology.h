@@ -12,7 +12,6 @@ namespace ebe {
 // the node: the owner writes per-node values that every touching patch computes.
 constexpr uint32_t kOwnerBit = 0x80000000u;
 constexpr int kMaxPatchElems = 256;  // one element per thread of a 256-thread workgroup
-constexpr int kDealWaves = 4;        // wavefronts per element workgroup (elements are dealt to them)
 
 // Element record used by the kernels: ten patch-local node indices (vertices
 // first, then edges in the conn order), the material id and one pad word.

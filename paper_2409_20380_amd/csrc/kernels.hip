@@ -1150,57 +1150,78 @@ __global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_
 // column in time order; a column whose remaining (orthogonal) part is below
 // drop * its norm is dropped, which reproduces the column selection of
 // modified Gram-Schmidt in that order.  Then R^T y = h, R a = y, coef = a / d.
+// Broadcast of lane l's value (l a compile-time constant in the unrolled loops below).
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// One wavefront per region; lane = column index throughout.  Each lane keeps
+// its column of the (scaled) Gram matrix in registers; row values of other
+// columns come by readlane at unrolled, compile-time lane indices, so the
+// factorisation has no LDS round trip and no barrier per pivot.  The column
+// oriented Cholesky with pivot drop, the forward and the back substitution
+// perform the same operations in the same order as a row-by-row
+// implementation (the back substitution reads R^T from one LDS copy).
 __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, int s, double drop, double* coef) {
-    __shared__ double G[32][33];
-    __shared__ double y[32], d[32];
-    __shared__ int keep[32];
+    __shared__ double R[32][33];
     const int r = blockIdx.x, lane = threadIdx.x;
     const double* in = gh + (int64_t)r * kGhStride;
-    // lane = column index throughout: row loops, no index division
-    for (int i = 0; i < s; ++i)
-        if (lane < s) G[i][lane] = in[i * 32 + lane];
-    if (lane < s) y[lane] = in[1024 + lane];
-    __syncthreads();
-    if (lane < s) {
-        d[lane] = sqrt(G[lane][lane]);
-        keep[lane] = 0;
+    const bool col = lane < s;
+    double g[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) g[i] = (col && i < s) ? in[i * 32 + lane] : 0.0;
+    double y = col ? in[1024 + lane] : 0.0;
+    const double dl = col ? sqrt(in[lane * 32 + lane]) : 0.0;
+    // scaling by the column norms: G_il / (d_i d_l), h_l / d_l
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const double di = lane_value(dl, i);
+        g[i] = (di > 0.0 && dl > 0.0) ? g[i] / (di * dl) : 0.0;
     }
-    __syncthreads();
-    for (int i = 0; i < s; ++i)
-        if (lane < s) G[i][lane] = (d[i] > 0.0 && d[lane] > 0.0) ? G[i][lane] / (d[i] * d[lane]) : 0.0;
-    if (lane < s) y[lane] = d[lane] > 0.0 ? y[lane] / d[lane] : 0.0;
-    __syncthreads();
+    y = dl > 0.0 ? y / dl : 0.0;
     const double drop2 = drop * drop;
-    for (int j = 0; j < s; ++j) {
-        const double t = G[j][j];
-        const bool kj = d[j] > 0.0 && t >= drop2;
-        const double rjj = kj ? sqrt(t) : 0.0;
-        __syncthreads();
-        if (lane > j && lane < s) G[j][lane] = kj ? G[j][lane] / rjj : 0.0;
-        if (lane == 0) {
-            G[j][j] = rjj;
-            keep[j] = kj;
+    uint32_t keep = 0;   // bit j: column j kept (uniform)
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+        if (j < s) {
+            const double t = lane_value(g[j], j);
+            const bool kj = lane_value(dl, j) > 0.0 && t >= drop2;
+            const double rjj = kj ? sqrt(t) : 0.0;
+            if (lane > j && col) g[j] = kj ? g[j] / rjj : 0.0;
+            if (lane == j) g[j] = rjj;
+            keep |= kj ? 1u << j : 0u;
+            if (kj) {   // trailing update of the upper triangle, column = lane
+#pragma unroll
+                for (int k = j + 1; k < 32; ++k) {
+                    const double gjk = lane_value(g[j], k);   // G[j][k] (row j, column k)
+                    if (k < s && k <= lane && col) g[k] -= gjk * g[j];
+                }
+            }
         }
-        __syncthreads();
-        if (kj && lane > j && lane < s) {  // trailing update of the upper triangle, column = lane
-            const double gjl = G[j][lane];
-            for (int k = j + 1; k <= lane; ++k) G[k][lane] -= G[j][k] * gjl;
+    }
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {     // R^T y = h (column-oriented)
+        if (j < s) {
+            if (lane == j) y = ((keep >> j) & 1) ? y / g[j] : 0.0;
+            const double yj = lane_value(y, j);
+            if (lane > j && col) y -= g[j] * yj;
         }
-        __syncthreads();
     }
-    for (int j = 0; j < s; ++j) {      // R^T y = h (column-oriented)
-        if (lane == j) y[j] = keep[j] ? y[j] / G[j][j] : 0.0;
-        __syncthreads();
-        if (lane > j && lane < s) y[lane] -= G[j][lane] * y[j];
-        __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        if (lane < 32) R[i][lane] = g[i];   // R[i][l] from lane l
+    __syncthreads();
+#pragma unroll
+    for (int j = 31; j >= 0; --j) {    // R a = y
+        if (j < s) {
+            if (lane == j) y = ((keep >> j) & 1) ? y / g[j] : 0.0;
+            const double yj = lane_value(y, j);
+            if (lane < j) y -= R[lane][j] * yj;
+        }
     }
-    for (int j = s - 1; j >= 0; --j) { // R a = y
-        if (lane == j) y[j] = keep[j] ? y[j] / G[j][j] : 0.0;
-        __syncthreads();
-        if (lane < j) y[lane] -= G[lane][j] * y[j];
-        __syncthreads();
-    }
-    if (lane < 32) coef[32 * (int64_t)r + lane] = (lane < s && keep[lane]) ? y[lane] / d[lane] : 0.0;
+    if (lane < 32) coef[32 * (int64_t)r + lane] = (col && ((keep >> lane) & 1)) ? y / dl : 0.0;
 }
 
 void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,

@@ -288,15 +288,43 @@ __device__ __forceinline__ void stage_materials(const DevPatches& P, double* lds
     stage_material_table(P, lmat, 64 * kEbeWaves);
 }
 
+// Apply / right-hand side: persistent grid as in the PCG matvec (each
+// workgroup walks a contiguous per-XCD range of patches, node entries loaded
+// one patch ahead).
 template <int MODE>
 __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
     if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
     extern __shared__ double lds[];
-    const int patch = xcd_remap(blockIdx.x, gridDim.x);
     stage_materials<MODE>(A.P, lds);
+    const int xcd = blockIdx.x & 7, k0 = blockIdx.x >> 3, per_xcd_wg = gridDim.x >> 3;   // grid: multiple of 8
+    const int chunk = A.P.n_patches_pad >> 3;
     PatchPre pf;
-    patch_prefetch(A.P, patch, pf);
-    ebe_patch<MODE, double, double>(A, patch, 0.0, lds, pf, -1);
+    if (k0 < chunk) patch_prefetch(A.P, xcd * chunk + k0, pf);
+    for (int k = k0; k < chunk; k += per_xcd_wg) {
+        const int kn = k + per_xcd_wg;
+        ebe_patch<MODE, double, double>(A, xcd * chunk + k, 0.0, lds, pf, kn < chunk ? xcd * chunk + kn : -1);
+    }
+}
+
+// Persistent grid of the apply / right-hand-side passes: the workgroups that
+// fit on the device at once (one or two per CU by LDS), a multiple of 8.
+int ebe_grid(const DevPatches& P, int mode) {
+    static int cus = 0, lds_cu = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
+            cus = 256;
+            lds_cu = 160 * 1024;
+        }
+    }
+    const size_t need = ebe_lds_bytes(P, mode);
+    int per_cu = need > 0 ? (int)(lds_cu / need) : 2;
+    per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
+    int g = cus * per_cu / 8 * 8;
+    if (g < 8) g = 8;
+    return g < P.n_patches_pad ? g : P.n_patches_pad;
 }
 
 // FP64 sizing; it also covers the FP32 operands of the low-precision variants.
@@ -417,8 +445,8 @@ void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool 
     EbeArgs A{};
     A.P = P; A.in0 = p; A.qbuf = qbuf; A.cm = cm; A.ck = ck; A.mask_in = mask_in ? 1 : 0;
     A.guard = guard;
-    hipLaunchKernelGGL(k_ebe<MODE_APPLY>, dim3(P.n_patches_pad), dim3(64 * kEbeWaves), ebe_lds_bytes(P, MODE_APPLY), s,
-                       A);
+    hipLaunchKernelGGL(k_ebe<MODE_APPLY>, dim3(ebe_grid(P, MODE_APPLY)), dim3(64 * kEbeWaves),
+                       ebe_lds_bytes(P, MODE_APPLY), s, A);
 }
 
 int pcg_ebe_grid(const DevPatches& P) {
@@ -449,7 +477,8 @@ void launch_ebe_rhs(hipStream_t s, const DevPatches& P, const double* u, const d
     EbeArgs A{};
     A.P = P; A.in0 = u; A.in1 = v; A.in2 = a; A.qbuf = qbuf; A.cm = 1.0; A.ck = 1.0;
     A.c1 = c1; A.c2 = c2; A.g0 = g0; A.g1 = g1; A.g2 = g2;
-    hipLaunchKernelGGL(k_ebe<MODE_RHS>, dim3(P.n_patches_pad), dim3(64 * kEbeWaves), ebe_lds_bytes(P, MODE_RHS), s, A);
+    hipLaunchKernelGGL(k_ebe<MODE_RHS>, dim3(ebe_grid(P, MODE_RHS)), dim3(64 * kEbeWaves), ebe_lds_bytes(P, MODE_RHS), s,
+                       A);
 }
 
 // ---------------------------------------------------------------------------

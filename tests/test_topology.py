@@ -1,0 +1,151 @@
+"""Host-side patch topology of the element kernels (paper_2409_20380_amd/csrc/topology.cpp), on the CPU.
+
+The element kernels stage each patch's nodes in LDS under patch-local ids; the
+ids are spread over the LDS bank pairs that an FP64 LDS atomic services
+together (8 lanes, 16 bank pairs on gfx950), by exchanging ids only between
+nodes of the same kind inside an aligned block of 64 ids.  These tests build
+the topology through a small probe compiled from the library's own source and
+check what the kernels rely on: every element appears once with its exact
+nodes, vertices keep the id prefix [0, nv), ids stay in their 64-id block,
+owner bits and node-major slots are consistent, and the bank conflicts of the
+atomics are actually reduced.
+"""
+import ctypes as C
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2409_20380_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2409_20380_amd", "csrc")
+OWNER = 0x80000000
+
+
+@pytest.fixture(scope="module")
+def probe():
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("no host C++ compiler")
+    d = tempfile.mkdtemp(prefix="topo_probe_")
+    so = os.path.join(d, "libprobe.so")
+    subprocess.check_call([gxx, "-O2", "-std=c++17", "-shared", "-fPIC", "-I", CSRC,
+                           os.path.join(ROOT, "tests", "topology_probe.cpp"), os.path.join(CSRC, "topology.cpp"),
+                           "-o", so])
+    yield C.CDLL(so)
+    shutil.rmtree(d, ignore_errors=True)
+
+
+def build(probe, wl, patch_elems=256):
+    mesh, em, mat, fx, regions, _ = wl.build()
+    a = lambda x, t: np.ascontiguousarray(x, dtype=t)
+    P = lambda x: x.ctypes.data_as(C.c_void_p)
+    xyz, conn, emm, matt = a(mesh.coords, np.float64), a(mesh.conn, np.int32), a(em, np.int32), a(mat, np.float64)
+    fxx, reg = a(fx, np.uint8), a(regions, np.int32)
+    rc = probe.probe_build(C.c_int64(mesh.n_nodes), P(xyz), C.c_int64(len(conn)), P(conn), P(emm),
+                           C.c_int(len(matt)), P(matt), P(fxx), P(reg), C.c_int(512), C.c_int(patch_elems))
+    assert rc == 0
+    sz = np.zeros(7, np.int64)
+    probe.probe_sizes(P(sz))
+    npat, ppad, pn, ne, max_pn, max_nv, nslot = (int(v) for v in sz)
+    el_ptr = np.zeros(ppad + 1, np.int32); pn_ptr = np.zeros(ppad + 1, np.int32); nv = np.zeros(ppad, np.int32)
+    nodes = np.zeros(pn, np.uint32); slot = np.zeros(pn, np.int32); lids = np.zeros((ne, 10), np.uint16)
+    slot_ptr = np.zeros(mesh.n_nodes + 1, np.int32); i2u = np.zeros(mesh.n_nodes, np.int32)
+    probe.probe_arrays(P(el_ptr), P(pn_ptr), P(nv), P(nodes), P(slot), P(lids), P(slot_ptr), P(i2u))
+    return dict(conn=conn, n=mesh.n_nodes, npat=npat, ppad=ppad, el_ptr=el_ptr, pn_ptr=pn_ptr, nv=nv, nodes=nodes,
+                slot=slot, lids=lids, slot_ptr=slot_ptr, i2u=i2u, max_pn=max_pn, patch_elems=patch_elems)
+
+
+def patches(t):
+    for p in range(t["ppad"]):
+        e0, e1 = t["el_ptr"][p], t["el_ptr"][p + 1]
+        n0, n1 = t["pn_ptr"][p], t["pn_ptr"][p + 1]
+        yield p, e0, e1, n0, n1
+
+
+def bank_multiplicity(lids, lane_group=8, bank_pairs=16):
+    """Mean over (group of 8 consecutive elements, element position) of the largest number of
+    lanes whose accumulator double 3 l + c falls on one bank pair."""
+    worst = []
+    for g0 in range(0, len(lids), lane_group):
+        grp = lids[g0:g0 + lane_group].astype(np.int64)
+        for i in range(10):
+            worst.append(np.bincount((3 * grp[:, i]) % bank_pairs, minlength=bank_pairs).max())
+    return float(np.mean(worst))
+
+
+CASES = [(inputs.SMALL, 256), (inputs.SMALL, 64),
+         (inputs.Workload("box3x5x2_ragged", cells=(3, 5, 2), nt=30, s=6, region_block=4), 256)]
+
+
+@pytest.mark.parametrize("wl,pe", CASES, ids=["8x8x8_256", "8x8x8_64", "3x5x2_256"])
+def test_patch_topology_invariants(probe, wl, pe):
+    t = build(probe, wl, pe)
+    conn = t["conn"]
+    want = {}
+    for e, row in enumerate(conn):
+        want.setdefault(tuple(int(v) for v in row), []).append(e)
+    seen = {}
+    owners = np.zeros(t["n"], np.int64)
+    patches_of = [[] for _ in range(t["n"])]
+    assert t["ppad"] % 8 == 0 and t["ppad"] >= t["npat"]
+    for p, e0, e1, n0, n1 in patches(t):
+        assert e1 - e0 <= pe
+        ent = t["nodes"][n0:n1]
+        internal = (ent & ~np.uint32(OWNER)).astype(np.int64)
+        npn, nv = n1 - n0, int(t["nv"][p])
+        assert npn <= t["max_pn"] and len(set(internal.tolist())) == npn
+        used = np.zeros(npn, bool)
+        for k in range(e0, e1):
+            lid = t["lids"][k].astype(np.int64)
+            assert (lid < npn).all()
+            assert (lid[:4] < nv).all() and (lid[4:] >= nv).all()   # vertices first
+            used[lid] = True
+            key = tuple(int(t["i2u"][internal[l]]) for l in lid)     # element nodes in connectivity order
+            assert key in want, (p, k)
+            seen[key] = seen.get(key, 0) + 1
+        assert used.all()   # the patch lists exactly its elements' nodes
+        for l, v in enumerate(internal):
+            patches_of[v].append(p)
+            if ent[l] & OWNER:
+                owners[v] += 1
+                assert len(patches_of[v]) == 1   # owner = first patch of the node
+        # ids move only inside their aligned 64-id block (same kind): the unspread numbering is
+        # vertices by internal id, then edge nodes by internal id
+        order = np.concatenate([np.sort(internal[:nv]), np.sort(internal[nv:])])
+        pos = {int(v): i for i, v in enumerate(order)}
+        for new_id, v in enumerate(internal):
+            assert pos[int(v)] // 64 == new_id // 64
+    assert all(seen.get(k, 0) == len(v) for k, v in want.items()) and sum(seen.values()) == len(conn)
+    assert (owners == 1).all()
+    counts = np.diff(t["slot_ptr"])
+    assert (counts == np.array([len(x) for x in patches_of])).all() and t["slot_ptr"][-1] == len(t["nodes"])
+    for p, e0, e1, n0, n1 in patches(t):   # node-major slots in patch order
+        for l in range(n0, n1):
+            v = int(t["nodes"][l] & ~np.uint32(OWNER))
+            assert t["slot"][l] == t["slot_ptr"][v] + patches_of[v].index(p)
+
+
+def test_bank_spreading_reduces_conflicts(probe):
+    """Full 256-element patches of the 8x8x8 mesh: the spread ids put the 8 lanes of an atomic on distinct
+    bank pairs far more often than the plain (sorted) numbering of the same patches would."""
+    t = build(probe, inputs.SMALL, 256)
+    spread, plain = [], []
+    for p, e0, e1, n0, n1 in patches(t):
+        if e1 - e0 < 256:
+            continue
+        internal = (t["nodes"][n0:n1] & ~np.uint32(OWNER)).astype(np.int64)
+        nv = int(t["nv"][p])
+        order = np.concatenate([np.sort(internal[:nv]), np.sort(internal[nv:])])
+        pos = {int(v): i for i, v in enumerate(order)}
+        lids = t["lids"][e0:e1].astype(np.int64)
+        plain_lids = np.vectorize(lambda l: pos[int(internal[l])])(lids)
+        spread.append(bank_multiplicity(lids))
+        plain.append(bank_multiplicity(plain_lids))
+    assert spread, "no full patch"
+    assert np.mean(spread) < 1.25, np.mean(spread)
+    assert np.mean(spread) < np.mean(plain) - 0.5, (np.mean(spread), np.mean(plain))

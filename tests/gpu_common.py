@@ -91,3 +91,6 @@ def history_columns(ring, it, s):
 
 SMALL = inputs.SMALL
 RAGGED = inputs.Workload("box3x5x2_ragged", cells=(3, 5, 2), nt=30, s=6, region_block=4)
+# the same 8x8x8-cell lattice with 1/8 m cells (a 1 m box): a correctness-only case whose
+# condition number is about 400 times that of the 2.5 m cells (hundreds of trips per step)
+LITERAL = inputs.Workload("box8x8x8_h0.125", cells=(8, 8, 8), h=0.125, nt=40, s=16)

@@ -9,8 +9,8 @@ import numpy as np
 import pytest
 
 from paper_2409_20380_amd import inputs
-from tests.gpu_common import (RAGGED, SMALL, build_case, cm_ck, history_columns, rel_max, sampled_rows, to_dev,
-                              to_host)
+from tests.gpu_common import (LITERAL, RAGGED, SMALL, build_case, cm_ck, history_columns, rel_max, sampled_rows,
+                              to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,6 +32,12 @@ def small(oracle_lib):
 def ragged(oracle_lib):
     say("build ragged workload", RAGGED.cells)
     return build_case(RAGGED, oracle_lib, patch_elems=17)
+
+
+@pytest.fixture(scope="module")
+def literal(oracle_lib):
+    say("build 1 m box workload", LITERAL.cells, "h", LITERAL.h)
+    return build_case(LITERAL, oracle_lib)
 
 
 def test_version_and_regions(small):
@@ -263,7 +269,7 @@ def _gpu_run(sol, wave, nt):
     return np.array(U), np.array(its), np.array(res)
 
 
-@pytest.mark.parametrize("case", ["small", "ragged"])
+@pytest.mark.parametrize("case", ["small", "ragged", "literal"])
 def test_trajectory_matches_oracle(case, request, oracle_lib):
     c = request.getfixturevalue(case)
     wl = c["wl"]
@@ -278,8 +284,14 @@ def test_trajectory_matches_oracle(case, request, oracle_lib):
     say("space-time rel L2 vs tight oracle", err, "iters gpu/oracle", its.mean(), its8.mean())
     assert err < TRAJ_TOL
     assert (res < wl.tol).all()
-    # true residual of the final step re-evaluated by the oracle's assembled operator
-    assert np.abs(its - its8).max() <= 3
+    if case == "literal":
+        # At 1/8 m cells (condition number ~1e5) the trip count of a step is not a stable
+        # quantity: the oracle itself, fed the same wave scaled by 1 + 1e-13, moves single
+        # steps by up to 18 of ~330 trips while its mean moves by 0.6 %. Only the mean is
+        # compared there; the trajectory and residual checks above are the same as elsewhere.
+        assert abs(its.mean() - its8.mean()) <= 0.02 * its8.mean()
+    else:
+        assert np.abs(its - its8).max() <= 3
     if case == "small":
         # trend of the paper's Fig. 3 (not an exact pin): the data-driven predictor
         # needs fewer iterations than Adams-Bashforth alone once its window is full

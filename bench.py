@@ -231,7 +231,8 @@ def run_learned(args):
     solver generates (own kernels), then compare test trajectories of kind 3
     (network candidate with fallback) with the plain method (kind 2) and with
     kind 3 on a zero network (the fallback between AB4 and the snapshot guess
-    alone)."""
+    alone); then kinds 2 and 3 again with the FP32 inner solve (the learned
+    guess and mixed precision together)."""
     import numpy as np
     import torch
 
@@ -259,18 +260,19 @@ def run_learned(args):
     t_train = time.time() - t0
     trained, scales = sol.mlp_get()
 
-    def run(kind, seeds_, params, timing=False):
-        sol.set_predictor(kind)
+    def run(kind, seeds_, params, solver=None):
+        solver = sol if solver is None else solver
+        solver.set_predictor(kind)
         if params is not None:
-            sol.mlp_set(params, scales)
+            solver.mlp_set(params, scales)
         its, res, picks, el = [], [], [], 0.0
         for seed in seeds_:
             w = inputs.base_wave(seed, args.test_steps, wl.dt, *wl.f_band)
-            sol.reset()
+            solver.reset()
             torch.cuda.synchronize()
             t = time.perf_counter()
             for it in range(1, args.test_steps + 1):
-                st = sol.step(base_acc=w[it])
+                st = solver.step(base_acc=w[it])
                 if st.status != 0:
                     raise RuntimeError(f"seed {seed} step {it} did not converge")
                 its.append(st.iters); res.append(st.res_true); picks.append(st.learned)
@@ -291,6 +293,17 @@ def run_learned(args):
     zero = run(ebe.PRED_LEARNED, test[:4], np.zeros_like(trained))
     log(f"selection only (kind 3, zero network, {min(4, len(test))} seeds): {zero}")
     sol.close()
+    # the two single-case growth forms together: the trained network's guess refined by the
+    # flexible FP64 PCG with the FP32 inner solve, against the same FP32 refine with the plain guess
+    solm = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems, precision=ebe.PREC_FP32,
+                      inner_iters=args.inner_iters, inner_tol=args.inner_tol)
+    solm.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
+    inner_trips = solm.effective_config().inner_iters
+    mixed_plain = run(ebe.PRED_SNAPSHOT, test, None, solm)
+    log(f"plain guess, FP32 inner solve: {mixed_plain}")
+    mixed_learned = run(ebe.PRED_LEARNED, test, trained, solm)
+    log(f"learned guess, FP32 inner solve: {mixed_learned}")
+    solm.close()
     bpe = ebe_pcg_bytes_per_element(mesh.n_nodes, mesh.n_elems)
     achieved = bpe * mesh.n_elems / (ebe_ms * 1e-3) / 1e9 if ebe_ms > 0 else 0.0
     out = {
@@ -318,7 +331,15 @@ def run_learned(args):
         "plain_cg_iters_per_step": plain["iters"],
         "learned_pick_fraction": learned["pick"],
         "selection_only": zero,
-        "max_true_rel_residual": max(learned["max_res"], plain["max_res"]),
+        "learned_fp32_inner": {"value": mixed_learned["value"], "ms_per_step": mixed_learned["ms_per_step"],
+                               "cg_iters_per_step": mixed_learned["iters"], "max_res": mixed_learned["max_res"],
+                               "speedup_vs_plain": mixed_learned["value"] / plain["value"],
+                               "inner_trips": inner_trips},
+        "plain_fp32_inner": {"value": mixed_plain["value"], "ms_per_step": mixed_plain["ms_per_step"],
+                             "cg_iters_per_step": mixed_plain["iters"], "max_res": mixed_plain["max_res"],
+                             "speedup_vs_plain": mixed_plain["value"] / plain["value"]},
+        "max_true_rel_residual": max(learned["max_res"], plain["max_res"], mixed_learned["max_res"],
+                                     mixed_plain["max_res"]),
         "train_seconds": {"generate": t_gen, "train": t_train},
         "final_train_loss": float(np.mean(losses[-50:])),
         "roofline": {"kernel": "k_ebe<PCG> (fused direction update + EBE matvec + (p,Ap))", "bound": "hbm",

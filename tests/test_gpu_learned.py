@@ -206,13 +206,11 @@ def test_predict_learned_matches_oracle(small, oracle_lib):
     sol.reset()
 
 
-def test_learned_steps_keep_the_better_guess_and_the_answer(small, oracle_lib):
+def _kind3_trajectory(c, oracle_lib):
     """Kind 3 with an untrained network: per step the kept guess has the smaller
     initial residual, and the trajectory is the oracle's to the tolerance."""
     from paper_2409_20380_amd import ebe
-    c = small
     wl, sol = c["wl"], c["sol"]
-    say("kind 3 trajectory, untrained network")
     sol.reset()
     sol.mlp_set(bf16_params(51, gain=0.2), [1e-3, 1e-4, 1e4, 1e-6])
     sol.set_predictor(ebe.PRED_LEARNED)
@@ -242,6 +240,23 @@ def test_learned_steps_keep_the_better_guess_and_the_answer(small, oracle_lib):
     assert err < 1e-6
     sol.set_predictor(ebe.PRED_SNAPSHOT)
     sol.reset()
+
+
+def test_learned_steps_keep_the_better_guess_and_the_answer(small, oracle_lib):
+    say("kind 3 trajectory, untrained network, FP64 refine")
+    _kind3_trajectory(small, oracle_lib)
+
+
+def test_learned_steps_with_mixed_precision_refine(oracle_lib):
+    """The learned guess composes with the FP32 inner solve: same selection rule,
+    same answer to the tolerance."""
+    from paper_2409_20380_amd import ebe
+    say("kind 3 trajectory, untrained network, FP32 inner solve")
+    c = build_case(SMALL, oracle_lib, precision=ebe.PREC_FP32)
+    try:
+        _kind3_trajectory(c, oracle_lib)
+    finally:
+        c["sol"].close()
 
 
 @pytest.mark.slow

@@ -359,3 +359,75 @@ def test_full_size_apply_sampled_rows(oracle_lib):
     lhs, rhs = p @ Ay, y @ q.ravel()
     assert abs(lhs - rhs) < 1e-12 * abs(lhs) * 100
     sol.close()
+
+
+def _one_tet():
+    """A single straight 10-node tet (vertices, then edges 01, 12, 02, 03, 13, 23)."""
+    v = np.array([[0.0, 0.0, 0.0], [2.5, 0.0, 0.0], [0.0, 2.5, 0.0], [0.0, 0.0, 2.5]])
+    edges = [(0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3)]
+    coords = np.vstack([v] + [0.5 * (v[a] + v[b]) for a, b in edges])
+    conn = np.arange(10, dtype=np.int32)[None, :]
+    fixed = np.zeros((10, 3), dtype=np.uint8)
+    fixed[0, :] = 1                      # one vertex held; the mass keeps A definite anyway
+    fixed[1, 2] = 1
+    return coords, conn, np.zeros(1, np.int32), np.array([[1800.0, 380.0, 200.0]]), fixed
+
+
+def test_single_element_mesh(oracle_lib):
+    """One element, one patch of one element, one region: apply and a short
+    trajectory (the snapshot window never fills) against the oracle."""
+    from paper_2409_20380_amd import ebe
+    coords, conn, em, mat, fx = _one_tet()
+    wl = SMALL
+    aR, bR = wl.rayleigh
+    cM, cK = cm_ck(wl.dt, aR, bR)
+    regions = np.zeros(10, np.int32)
+    say("single element: 10 nodes, 1 element, s 4")
+    m = oracle_lib.Model(coords, conn, em, mat, fx, cM, cK)
+    sol = ebe.Solver(wl.dt, aR, bR, s=4, tol=wl.tol)
+    sol.assemble(coords, conn, em, mat, fx, regions)
+    for seed in (0, 1):
+        p = inputs.random_vector(seed, 30)
+        assert rel_max(to_host(sol.apply(to_dev(p))), m.spmv("A", p)) < APPLY_TOL
+    wave = inputs.base_wave(3, 12, wl.dt, *wl.f_band)
+    U, its = [], []
+    for it in range(1, 13):
+        st = sol.step(base_acc=wave[it])
+        assert st.status == 0 and st.res_true < wl.tol
+        U.append(to_host(sol.get_state()[0])); its.append(st.iters)
+    orc = oracle_lib.Stepper(m, wl.dt, aR, bR, s=4, kind=2, tol=1e-13, regions=regions)
+    o8 = oracle_lib.Stepper(m, wl.dt, aR, bR, s=4, kind=2, tol=wl.tol, regions=regions)
+    Uref, its8 = [], []
+    for it in range(1, 13):
+        orc.step(g=wave[it])
+        rec, _, _ = o8.step(g=wave[it])
+        Uref.append(orc.u.copy()); its8.append(rec.iters)
+    err = np.linalg.norm(np.array(U) - np.array(Uref)) / np.linalg.norm(np.array(Uref))
+    say("single element: space-time rel L2", err, "iters", its, its8)
+    assert err < TRAJ_TOL
+    assert np.abs(np.array(its) - np.array(its8)).max() <= 3
+    sol.close()
+
+
+def test_all_dofs_fixed():
+    """Every dof fixed: A is the identity, every right-hand side is zero, so each
+    step takes no trip and the state stays exactly at rest (zero Gram columns
+    are dropped by the least-squares solve)."""
+    from paper_2409_20380_amd import ebe
+    mesh = inputs.box_mesh(1, 1, 1)
+    em, mat = inputs.two_layer_materials(mesh)
+    fx = np.ones((mesh.n_nodes, 3), dtype=np.uint8)
+    wl = SMALL
+    aR, bR = wl.rayleigh
+    say("all dofs fixed: 1x1x1 cells,", mesh.n_nodes, "nodes")
+    sol = ebe.Solver(wl.dt, aR, bR, s=4, tol=wl.tol)
+    sol.assemble(mesh.coords, mesh.conn, em, mat, fx)
+    p = inputs.random_vector(4, 3 * mesh.n_nodes)
+    np.testing.assert_array_equal(to_host(sol.apply(to_dev(p))), p)
+    wave = inputs.base_wave(5, 10, wl.dt, *wl.f_band)
+    for it in range(1, 11):
+        st = sol.step(base_acc=wave[it])
+        assert st.status == 0 and st.iters == 0
+    for vec in sol.get_state():
+        assert float(vec.abs().max()) == 0.0
+    sol.close()

@@ -15,6 +15,7 @@ import os
 import shutil
 import subprocess
 import tempfile
+import types
 
 import numpy as np
 import pytest
@@ -78,11 +79,27 @@ def bank_multiplicity(lids, lane_group=8, bank_pairs=16):
     return float(np.mean(worst))
 
 
+class OneTet:
+    """A single straight 10-node tet (vertices, then edges 01, 12, 02, 03, 13, 23): one patch of one element."""
+
+    @staticmethod
+    def build():
+        v = np.array([[0.0, 0.0, 0.0], [2.5, 0.0, 0.0], [0.0, 2.5, 0.0], [0.0, 0.0, 2.5]])
+        edges = [(0, 1), (1, 2), (0, 2), (0, 3), (1, 3), (2, 3)]
+        coords = np.vstack([v] + [0.5 * (v[a] + v[b]) for a, b in edges])
+        mesh = types.SimpleNamespace(coords=coords, conn=np.arange(10, dtype=np.int32)[None, :], n_nodes=10)
+        fixed = np.zeros((10, 3), np.uint8)
+        fixed[0] = 1
+        return (mesh, np.zeros(1, np.int32), np.array([[1800.0, 380.0, 200.0]]), fixed, np.zeros(10, np.int32),
+                None)
+
+
 CASES = [(inputs.SMALL, 256), (inputs.SMALL, 64),
-         (inputs.Workload("box3x5x2_ragged", cells=(3, 5, 2), nt=30, s=6, region_block=4), 256)]
+         (inputs.Workload("box3x5x2_ragged", cells=(3, 5, 2), nt=30, s=6, region_block=4), 256),
+         (OneTet, 256), (inputs.Workload("box1x1x1", cells=(1, 1, 1), nt=1, s=1), 1)]
 
 
-@pytest.mark.parametrize("wl,pe", CASES, ids=["8x8x8_256", "8x8x8_64", "3x5x2_256"])
+@pytest.mark.parametrize("wl,pe", CASES, ids=["8x8x8_256", "8x8x8_64", "3x5x2_256", "one_tet", "1x1x1_1"])
 def test_patch_topology_invariants(probe, wl, pe):
     t = build(probe, wl, pe)
     conn = t["conn"]

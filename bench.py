@@ -114,8 +114,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): this build has no "
-              "multi-GPU path; see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}): the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.txt"))
     ap.add_argument("--patch-elems", type=int, default=256, help="elements per EBE patch (1..256)")
+    ap.add_argument("--region-block", type=int, default=0,
+                    help="predictor regions of b^3 lattice nodes (0: the workload's, 8 = 512 nodes)")
     ap.add_argument("--workload", choices=["plain", "large", "learned", "ensemble"], default="plain")
     ap.add_argument("--no-graph", action="store_true", help="ensemble: enqueue PCG trips without hipGraph")
     ap.add_argument("--no-tune", action="store_true", help="ensemble: default case tiles instead of the autotuner")
@@ -135,7 +137,7 @@ def main():
     prec = {"fp64": ebe.PREC_FP64, "fp32": ebe.PREC_FP32, "bf16": ebe.PREC_BF16}[args.precision]
     nt = args.warmup + args.steps
     wl_run = inputs.Workload(wl.name, cells=wl.cells, h=wl.h, dt=wl.dt, nt=nt, s=wl.s, tol=wl.tol,
-                             seed=wl.seed, region_block=wl.region_block)
+                             seed=wl.seed, region_block=args.region_block or wl.region_block)
     mesh, em, mat, fx, regions, wave = wl_run.build()
     dof = 3 * mesh.n_nodes
     log(f"mesh {wl.cells}: {mesh.n_nodes} nodes, {dof} dof, {mesh.n_elems} elements")
@@ -203,7 +205,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": list(wl.cells), "nodes": mesh.n_nodes, "dof": dof,
                    "elements": mesh.n_elems, "dt": wl.dt, "snapshots": wl.s, "tol": wl.tol,
-                   "predictor": "AB4 + regional snapshot map", "timed_steps": f"{args.warmup + 1}-{nt}",
+                   "predictor": "AB4 + regional snapshot map", "region_nodes": wl_run.region_block ** 3,
+                   "timed_steps": f"{args.warmup + 1}-{nt}",
                    "refine": ("block-Jacobi PCG, FP64" if args.precision == "fp64" else
                               f"flexible FP64 PCG, inner {args.precision} PCG ({ecfg.inner_iters} trips, "
                               f"tol {ecfg.inner_tol:g})")},

@@ -55,7 +55,7 @@ struct ebe_handle {
     std::vector<void*> allocs;
     int32_t* d_i2u = nullptr;
     int32_t* d_u2i = nullptr;
-    int32_t* d_region_start = nullptr;
+    DevChunks chunks{};
     double* binv6 = nullptr;
     double* qbuf = nullptr;
     // state (internal node order)
@@ -448,8 +448,8 @@ int predict_into(ebe_handle* h, double* x) {
             int m = n - s_eff - 1 + j;  // e^m, stored in slot (m - 1) mod (s + 1)
             W.c[j] = h->ring_slot((m - 1) % S1);
         }
-        launch_gram_solve(s, W, s_eff, h->T.n_regions, h->d_region_start, h->cfg.drop_tol, h->gh, h->coef);
-        launch_pred_apply(s, W, s_eff, h->T.n_regions, h->d_region_start, h->coef, h->dab, x);
+        launch_gram_solve(s, W, s_eff, h->chunks, h->cfg.drop_tol, h->gh, h->coef);
+        launch_pred_apply(s, W, s_eff, h->chunks, h->coef, h->dab, x);
     }
     check_launch();
     return s_eff;
@@ -637,7 +637,8 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->free_all();
         Topology& T = h->T;
         std::string e = build_topology(T, n_nodes, coords, n_elems, conn, elem_mat, n_mat, mat, fixed,
-                                       region_of_node, h->cfg.region_nodes, h->cfg.patch_elems);
+                                       region_of_node, h->cfg.region_nodes, h->cfg.patch_elems,
+                                       ebe_patch_lds(n_mat));
         if (!e.empty()) throw Arg{e};
         hipStream_t s = h->stream;
         const int64_t N = T.n_nodes, n3 = 3 * N;
@@ -662,7 +663,11 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->dn.n = N;
         h->d_i2u = h->upload(T.i2u);
         h->d_u2i = h->upload(T.u2i);
-        h->d_region_start = h->upload(T.region_start);
+        h->chunks.n_regions = T.n_regions;
+        h->chunks.n_chunks = (int32_t)T.chunk_region.size();
+        h->chunks.start = h->upload(T.chunk_start);
+        h->chunks.region = h->upload(T.chunk_region);
+        h->chunks.first = h->upload(T.region_chunk);
         // buffers
         const size_t PN = T.patch_nodes.size();
         h->qbuf = h->alloc<double>(6 * PN);  // 6 entries per slot during setup, 3 afterwards
@@ -681,7 +686,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->t0 = h->alloc<double>(n3);
         h->t1 = h->alloc<double>(n3);
         h->coef = h->alloc<double>(32 * (size_t)T.n_regions);
-        h->gh = h->alloc<double>((size_t)kGhStride * T.n_regions);
+        h->gh = h->alloc<double>((size_t)kGhStride * T.chunk_region.size());
         h->sc = h->alloc<DevScalars>(1);
         h->pap_part = h->alloc<double>(pcg_ebe_grid(h->dp));
         h->res_part = h->alloc<double>(2 * kResArrays * (size_t)res_grid(N));

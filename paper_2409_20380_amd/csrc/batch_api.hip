@@ -113,8 +113,7 @@ struct ebe_batch {
     DevScalars* sc = nullptr;
     DevScalars* sc_host = nullptr;
     int* trip = nullptr;
-    int32_t* region_start = nullptr;
-    int n_regions = 0;
+    DevChunks chunks{};
     int head = 0, it = 0, par = 0, last_iters = 0;
     bool use_graph = true;
     int graph_trips = 8;
@@ -582,20 +581,30 @@ int ebe_batch_assemble(ebe_batch* b, int32_t tune) {
         BCHK(hipHostMalloc((void**)&b->sc_host, b->C * sizeof(DevScalars), hipHostMallocDefault));
         BCHK(hipHostMalloc((void**)&b->g_host, 3 * b->C * sizeof(double), hipHostMallocDefault));
         BCHK(hipMemsetAsync(b->sc, 0, b->C * sizeof(DevScalars), s));
-        // regions of every case of every group, in stacked node order
-        std::vector<int32_t> rs;
+        // regions of every case of every group, in stacked node order, cut into
+        // node chunks (the host vectors live until the stream is synchronised below)
+        if (nodes > INT32_MAX) throw BErr{EBE_E_INVALID_ARG, "batch too large"};
+        std::vector<int32_t> rs, cs, cr, rc;
         for (auto& g : b->groups) {
             const int64_t base = g.dof_off / 3;
             for (int c = 0; c < g.r; ++c)
                 for (int k = 0; k < g.T.n_regions; ++k) rs.push_back((int32_t)(base + c * g.N + g.T.region_start[k]));
         }
         rs.push_back((int32_t)nodes);
-        if (nodes > INT32_MAX) throw BErr{EBE_E_INVALID_ARG, "batch too large"};
-        b->n_regions = (int)rs.size() - 1;
-        b->region_start = M.alloc<int32_t>(rs.size());
-        BCHK(hipMemcpyAsync(b->region_start, rs.data(), rs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-        b->coef = M.alloc<double>(32 * (size_t)b->n_regions);
-        b->gh = M.alloc<double>((size_t)kGhStride * b->n_regions);
+        region_chunks(rs, cs, cr, rc);
+        b->chunks.n_regions = (int32_t)rs.size() - 1;
+        b->chunks.n_chunks = (int32_t)cr.size();
+        int32_t* d_cs = M.alloc<int32_t>(cs.size());
+        int32_t* d_cr = M.alloc<int32_t>(cr.size());
+        int32_t* d_rc = M.alloc<int32_t>(rc.size());
+        BCHK(hipMemcpyAsync(d_cs, cs.data(), cs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        BCHK(hipMemcpyAsync(d_cr, cr.data(), cr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        BCHK(hipMemcpyAsync(d_rc, rc.data(), rc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        b->chunks.start = d_cs;
+        b->chunks.region = d_cr;
+        b->chunks.first = d_rc;
+        b->coef = M.alloc<double>(32 * (size_t)b->chunks.n_regions);
+        b->gh = M.alloc<double>((size_t)kGhStride * b->chunks.n_chunks);
         // per group: block-Jacobi inverse (shared by its cases) and partials
         for (auto& g : b->groups) {
             g.binv6 = M.alloc<double>(6 * g.N);
@@ -709,8 +718,8 @@ int ebe_batch_step(ebe_batch* b, const double* base_acc, ebe_batch_stats* stats)
             ColPtrs W{};
             const int S1 = c.s + 1;
             for (int jj = 0; jj <= s_eff; ++jj) W.c[jj] = b->ring_slot((n - s_eff - 1 + jj - 1) % S1);
-            launch_gram_solve(s, W, s_eff, b->n_regions, b->region_start, c.drop_tol, b->gh, b->coef);
-            launch_pred_apply(s, W, s_eff, b->n_regions, b->region_start, b->coef, b->dab, b->x);
+            launch_gram_solve(s, W, s_eff, b->chunks, c.drop_tol, b->gh, b->coef);
+            launch_pred_apply(s, W, s_eff, b->chunks, b->coef, b->dab, b->x);
         }
         check_launch();
         int rc = solve_batch(b);

@@ -106,6 +106,7 @@ void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, d
 // Dynamic LDS of the element kernels for this topology, and the opt-in that
 // lets them use more than the default 64 KiB (returns false if refused).
 size_t ebe_lds_bytes(const DevPatches& P, int mode);
+PatchLds ebe_patch_lds(int32_t n_mat);
 bool ebe_set_lds_limit(const DevPatches& P);
 
 // ---- node-wise kernels
@@ -151,11 +152,19 @@ void launch_to_f32(hipStream_t s, int64_t n, const double* in, float* out);
 // ---- predictor and time integration (all lengths in dofs, 3N)
 void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const double* v2, const double* v3,
                 const double* v4, int kind, double* dab, double* x);
-constexpr int kGhStride = 32 * 32 + 32;   // per-region Gram [32][32] followed by X^T q [32]
-void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
-                       double drop, double* gh, double* coef);
-void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
-                       const double* coef, const double* dab, double* x);
+constexpr int kGhStride = 32 * 32 + 32;   // per-chunk Gram [32][32] followed by X^T q [32]
+// Predictor regions cut into node chunks (device arrays; see region_chunks).
+struct DevChunks {
+    int32_t n_regions = 0, n_chunks = 0;
+    const int32_t* start = nullptr;    // [n_chunks+1] internal node ranges
+    const int32_t* region = nullptr;   // [n_chunks] region of each chunk
+    const int32_t* first = nullptr;    // [n_regions+1] first chunk of each region
+};
+// gh: [n_chunks][kGhStride] partial Grams; coef: [n_regions][32].
+void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double drop, double* gh,
+                       double* coef);
+void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, const double* coef,
+                       const double* dab, double* x);
 void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, const double* dab, double* u,
                     const double* v_old, double* v_new, double* a, double* ring_slot);
 void launch_gather3(hipStream_t s, int64_t n, const int32_t* idx, const double* in, double* out);

@@ -308,17 +308,42 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
 
 // Persistent grid of the apply / right-hand-side passes: the workgroups that
 // fit on the device at once (one or two per CU by LDS), a multiple of 8.
-int ebe_grid(const DevPatches& P, int mode) {
-    static int cus = 0, lds_cu = 0;
-    if (!cus) {
+static void device_limits(int& cus, int& lds_cu) {
+    static int c = 0, l = 0;
+    if (!c) {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
-            cus = 256;
-            lds_cu = 160 * 1024;
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipDeviceGetAttribute(&l, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
+            c = 256;
+            l = 160 * 1024;
         }
     }
+    cus = c;
+    lds_cu = l;
+}
+
+// The patch builder's LDS limit: the element pass of the PCG loop keeps two
+// workgroups per CU.
+PatchLds ebe_patch_lds(int32_t n_mat) {
+    int cus = 0, lds_cu = 0;
+    device_limits(cus, lds_cu);
+    DevPatches z{};
+    z.n_mat = n_mat;
+    PatchLds L;
+    L.fixed = (int64_t)ebe_lds_bytes(z, MODE_PCG);
+    z.max_pn = 1;
+    L.per_node = (int64_t)ebe_lds_bytes(z, MODE_PCG) - L.fixed;
+    z.max_pn = 0;
+    z.max_nv = 1;
+    L.per_vertex = (int64_t)ebe_lds_bytes(z, MODE_PCG) - L.fixed;
+    L.budget = lds_cu / 2;
+    return L;
+}
+
+int ebe_grid(const DevPatches& P, int mode) {
+    int cus = 0, lds_cu = 0;
+    device_limits(cus, lds_cu);
     const size_t need = ebe_lds_bytes(P, mode);
     int per_cu = need > 0 ? (int)(lds_cu / need) : 2;
     per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);
@@ -450,8 +475,9 @@ void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool 
 }
 
 int pcg_ebe_grid(const DevPatches& P) {
-    int g = P.n_patches_pad < kMaxPcgGrid ? P.n_patches_pad : kMaxPcgGrid;
-    return g;   // n_patches_pad and kMaxPcgGrid are multiples of 8, so is g
+    // the resident workgroups (ebe_grid), at most kMaxPcgGrid; all multiples of 8
+    const int g = ebe_grid(P, MODE_PCG);
+    return g < kMaxPcgGrid ? g : kMaxPcgGrid;
 }
 
 void launch_ebe_pcg(hipStream_t s, const PcgLaunch& L) {
@@ -1084,7 +1110,9 @@ void launch_ab4(hipStream_t s, int64_t n3, double dt, const double* v1, const do
 // region's rows of W = [x_1 .. x_s, q]: X^T X from 16x16 tiles and X^T q from
 // per-lane FMAs, written to gh[r] = [32][32] Gram followed by [32] X^T q.
 template <int NB>
-__global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_t* region_start, double* gh) {
+// Partial Gram of one node chunk (one workgroup): G = X^T X over the chunk's
+// rows for the s_eff input columns, and X^T q for the query column s_eff.
+__global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_t* chunk_start, double* gh) {
     constexpr int NC = 16 * NB;
     constexpr int TR = 128;          // rows per LDS tile
     constexpr int LD = TR + 1;       // odd stride: the 16 columns read by one MFMA operand hit distinct banks
@@ -1094,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_
     double (*Gw)[NT][4][64] = reinterpret_cast<double (*)[NT][4][64]>(tile);   // reuses the tile after the loop
     static_assert(4 * NT * 4 * 64 <= (NC + 1) * LD, "per-wave tiles must fit in the staging buffer");
     const int r = blockIdx.x;
-    const int64_t d0 = 3 * (int64_t)region_start[r], d1 = 3 * (int64_t)region_start[r + 1];
+    const int64_t d0 = 3 * (int64_t)chunk_start[r], d1 = 3 * (int64_t)chunk_start[r + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, krow = lane >> 4;
     const int ncols = s_eff + 1;     // X columns and the query
@@ -1174,7 +1202,8 @@ __global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_
         out[1024 + threadIdx.x] = (hq[0][threadIdx.x] + hq[1][threadIdx.x]) + (hq[2][threadIdx.x] + hq[3][threadIdx.x]);
 }
 
-// Least-squares coefficients of one region (one 64-lane workgroup): with
+// Least-squares coefficients of one region (one 64-lane workgroup): the
+// region's Gram is the sum of its chunks' partial Grams, in chunk order; with
 // column scaling d_j = sqrt(G_jj), Cholesky of the scaled Gram taken column by
 // column in time order; a column whose remaining (orthogonal) part is below
 // drop * its norm is dropped, which reproduces the column selection of
@@ -1193,16 +1222,22 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // oriented Cholesky with pivot drop, the forward and the back substitution
 // perform the same operations in the same order as a row-by-row
 // implementation (the back substitution reads R^T from one LDS copy).
-__global__ __launch_bounds__(64) void k_ls_solve(const double* gh, int s, double drop, double* coef) {
+__global__ __launch_bounds__(64) void k_ls_solve(const double* gh, const int32_t* region_chunk, int s, double drop,
+                                                 double* coef) {
     __shared__ double R[32][33];
     const int r = blockIdx.x, lane = threadIdx.x;
-    const double* in = gh + (int64_t)r * kGhStride;
     const bool col = lane < s;
-    double g[32];
+    double g[32], y = 0.0, gll = 0.0;   // g[i] = G[i][lane]; gll = G[lane][lane], summed in the same order
 #pragma unroll
-    for (int i = 0; i < 32; ++i) g[i] = (col && i < s) ? in[i * 32 + lane] : 0.0;
-    double y = col ? in[1024 + lane] : 0.0;
-    const double dl = col ? sqrt(in[lane * 32 + lane]) : 0.0;
+    for (int i = 0; i < 32; ++i) g[i] = 0.0;
+    for (int c = region_chunk[r]; c < region_chunk[r + 1]; ++c) {
+        const double* in = gh + (int64_t)c * kGhStride;
+#pragma unroll
+        for (int i = 0; i < 32; ++i) g[i] += (col && i < s) ? in[i * 32 + lane] : 0.0;
+        y += col ? in[1024 + lane] : 0.0;
+        gll += col ? in[lane * 32 + lane] : 0.0;
+    }
+    const double dl = col ? sqrt(gll) : 0.0;
     // scaling by the column norms: G_il / (d_i d_l), h_l / d_l
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
@@ -1253,23 +1288,24 @@ __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, int s, double
     if (lane < 32) coef[32 * (int64_t)r + lane] = (col && ((keep >> lane) & 1)) ? y / dl : 0.0;
 }
 
-void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
-                       double drop, double* gh, double* coef) {
+void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double drop, double* gh,
+                       double* coef) {
     if (s_eff <= 16)
-        hipLaunchKernelGGL(k_gram<1>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, gh);
+        hipLaunchKernelGGL(k_gram<1>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
     else
-        hipLaunchKernelGGL(k_gram<2>, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, gh);
-    hipLaunchKernelGGL(k_ls_solve, dim3(n_regions), dim3(64), 0, s, gh, s_eff, drop, coef);
+        hipLaunchKernelGGL(k_gram<2>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
+    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(64), 0, s, gh, C.first, s_eff, drop, coef);
 }
 
-// x = dab + sum_j a_j y_j on each region, y_j = W.c[j + 1] (outputs).
-// x = dab + sum_j coef_j Y_j per region.  (A fully unrolled variant with all
-// 32 column loads of a row in flight measured slower, 228 vs 195 us.)
-__global__ __launch_bounds__(256) void k_pred_apply(ColPtrs W, int s_eff, const int32_t* region_start,
-                                                    const double* coef, const double* dab, double* x) {
-    const int r = blockIdx.x;
-    const int64_t d0 = 3 * (int64_t)region_start[r], d1 = 3 * (int64_t)region_start[r + 1];
-    const double* a = coef + 32 * (int64_t)r;
+// x = dab + sum_j coef_j Y_j on each node chunk with its region's
+// coefficients, Y_j = W.c[j + 1] (outputs).  (A fully unrolled variant with
+// all 32 column loads of a row in flight measured slower, 228 vs 195 us.)
+__global__ __launch_bounds__(256) void k_pred_apply(ColPtrs W, int s_eff, const int32_t* chunk_start,
+                                                    const int32_t* chunk_region, const double* coef,
+                                                    const double* dab, double* x) {
+    const int c = blockIdx.x;
+    const int64_t d0 = 3 * (int64_t)chunk_start[c], d1 = 3 * (int64_t)chunk_start[c + 1];
+    const double* a = coef + 32 * (int64_t)chunk_region[c];
     for (int64_t i = d0 + threadIdx.x; i < d1; i += 256) {
         double t = dab[i];
 #pragma unroll 8
@@ -1278,9 +1314,9 @@ __global__ __launch_bounds__(256) void k_pred_apply(ColPtrs W, int s_eff, const 
     }
 }
 
-void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, int n_regions, const int32_t* region_start,
-                       const double* coef, const double* dab, double* x) {
-    hipLaunchKernelGGL(k_pred_apply, dim3(n_regions), dim3(256), 0, s, W, s_eff, region_start, coef, dab, x);
+void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, const double* coef,
+                       const double* dab, double* x) {
+    hipLaunchKernelGGL(k_pred_apply, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, C.region, coef, dab, x);
 }
 
 // Newmark-beta (beta = 1/4, gamma = 1/2): u += du; v' = -v + (2/dt) du;

@@ -152,16 +152,35 @@ static void spread_banks(int ne, const std::vector<std::array<int32_t, 10>>& el_
     }
 }
 
-static char g_buf[512];
 template <class... A>
 static std::string fmt(const char* f, A... a) {
-    std::snprintf(g_buf, sizeof(g_buf), f, a...);
-    return std::string(g_buf);
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), f, a...);
+    return std::string(buf);
+}
+
+void region_chunks(const std::vector<int32_t>& region_start, std::vector<int32_t>& chunk_start,
+                   std::vector<int32_t>& chunk_region, std::vector<int32_t>& region_chunk) {
+    const int32_t R = (int32_t)region_start.size() - 1;
+    chunk_start.clear();
+    chunk_region.clear();
+    region_chunk.assign(R + 1, 0);
+    for (int32_t r = 0; r < R; ++r) {
+        const int64_t a = region_start[r], len = region_start[r + 1] - a;
+        const int64_t n = std::max<int64_t>(1, std::min<int64_t>(kMaxRegionChunks, (len + kChunkNodes - 1) / kChunkNodes));
+        region_chunk[r] = (int32_t)chunk_start.size();
+        for (int64_t k = 0; k < n; ++k) {
+            chunk_start.push_back((int32_t)(a + len * k / n));
+            chunk_region.push_back(r);
+        }
+    }
+    region_chunk[R] = (int32_t)chunk_start.size();
+    chunk_start.push_back(R > 0 ? region_start[R] : 0);
 }
 
 std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, const int32_t* conn,
                            const int32_t* elem_mat, int32_t n_mat, const double* mat, const uint8_t* fixed,
-                           const int32_t* region_of_node, int region_nodes, int patch_elems) {
+                           const int32_t* region_of_node, int region_nodes, int patch_elems, const PatchLds& lds) {
     if (N <= 0 || E <= 0) return "mesh must have nodes and elements";
     if (N >= (int64_t)1 << 31 || E >= (int64_t)1 << 31) return "mesh too large for 32-bit ids";
     if (n_mat <= 0 || n_mat > 65535) return "n_mat must be in [1, 65535]";
@@ -263,6 +282,7 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     T.region_start.assign(T.n_regions + 1, 0);
     for (int64_t v = 0; v < N; ++v) T.region_start[T.region_user[v] + 1]++;
     for (int32_t r = 0; r < T.n_regions; ++r) T.region_start[r + 1] += T.region_start[r];
+    region_chunks(T.region_start, T.chunk_start, T.chunk_region, T.region_chunk);
     T.coords.resize(3 * N);
     T.fixmask.resize(N);
     for (int64_t i = 0; i < N; ++i) {
@@ -293,8 +313,35 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
         return emort[a] < emort[b];
     });
 
-    // ---- patches
-    int64_t P = (E + patch_elems - 1) / patch_elems;
+    // ---- patches: cut the element order into runs of at most patch_elems
+    // elements whose nodes fit the LDS budget
+    std::vector<int64_t> cut(1, 0);
+    {
+        std::vector<int64_t> mark(N, -1);   // last patch that listed the node
+        int64_t npn = 0, nvx = 0, cnt = 0;
+        for (int64_t k = 0; k < E; ++k) {
+            const int32_t* c = conn + 10 * (int64_t)eord[k];
+            const int64_t cur = (int64_t)cut.size() - 1;
+            int64_t add_n = 0, add_v = 0;
+            for (int i = 0; i < 10; ++i)
+                if (mark[c[i]] != cur) { ++add_n; add_v += i < 4; }
+            const bool over = lds.budget > 0 &&
+                              lds.fixed + lds.per_node * (npn + add_n) + lds.per_vertex * (nvx + add_v) > lds.budget;
+            if (cnt > 0 && (cnt == patch_elems || over)) {
+                cut.push_back(k);
+                npn = nvx = cnt = 0;
+                add_n = 10;
+                add_v = 4;
+            }
+            const int64_t now = (int64_t)cut.size() - 1;
+            for (int i = 0; i < 10; ++i) mark[c[i]] = now;
+            npn += add_n;
+            nvx += add_v;
+            ++cnt;
+        }
+        if (E > 0) cut.push_back(E);
+    }
+    int64_t P = (int64_t)cut.size() - 1;
     int64_t Ppad = (P + 7) / 8 * 8;
     T.n_patches = (int32_t)P;
     T.n_patches_pad = (int32_t)Ppad;
@@ -310,7 +357,7 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     std::vector<int32_t> dealt, newid, ordered;
     std::vector<std::array<int32_t, 10>> el_local;
     for (int64_t p = 0; p < Ppad; ++p) {
-        int64_t e0 = std::min<int64_t>(p * patch_elems, E), e1 = std::min<int64_t>(e0 + patch_elems, E);
+        const int64_t e0 = p < P ? cut[p] : E, e1 = p < P ? cut[p + 1] : E;
         T.patch_el_ptr[p + 1] = (int32_t)e1;
         // Deal the patch's spatially sorted elements round-robin to the
         // groups of 8 lanes (kLdsLaneGroup) of the workgroup: elements that

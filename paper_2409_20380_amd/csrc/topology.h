@@ -29,6 +29,7 @@ struct Topology {
     std::vector<int32_t> i2u, u2i;          // internal -> user, user -> internal
     std::vector<int32_t> region_user;       // region id per user node
     std::vector<int32_t> region_start;      // [n_regions+1] internal node ranges
+    std::vector<int32_t> chunk_start, chunk_region, region_chunk;   // region_chunks(region_start)
     std::vector<double> coords;             // [N][3] internal order
     std::vector<uint8_t> fixmask;           // [N] bit c = component c fixed, internal order
     // patches
@@ -49,10 +50,31 @@ struct Topology {
     std::vector<double> mat_lmr;
 };
 
+// The predictor's Gram and apply passes work on node chunks of the regions, so
+// that their parallelism does not depend on the region size: a region of n
+// nodes is cut into min(kMaxRegionChunks, ceil(n / kChunkNodes)) chunks of
+// near-equal length.  Outputs: chunk_start [C+1] internal node ranges,
+// chunk_region [C] region of each chunk, region_chunk [R+1] first chunk of
+// each region.  Chunks of one region are consecutive.
+constexpr int kChunkNodes = 512;
+constexpr int kMaxRegionChunks = 64;
+void region_chunks(const std::vector<int32_t>& region_start, std::vector<int32_t>& chunk_start,
+                   std::vector<int32_t>& chunk_region, std::vector<int32_t>& region_chunk);
+
+// LDS bytes that a patch needs in the element kernels: fixed + per_node * (patch
+// nodes) + per_vertex * (vertex nodes).  A patch is closed before it would
+// exceed budget (budget <= 0: no limit), so that the kernels keep the number
+// of resident workgroups per CU the budget was chosen for.
+struct PatchLds {
+    int64_t per_node = 0, per_vertex = 0, fixed = 0, budget = 0;
+};
+
 // Builds the topology; returns an empty string on success or an error message.
+// Patches take consecutive elements of the spatial element order, at most
+// patch_elems of them and within lds.
 std::string build_topology(Topology& T, int64_t n_nodes, const double* coords, int64_t n_elems,
                            const int32_t* conn, const int32_t* elem_mat, int32_t n_mat, const double* mat,
                            const uint8_t* fixed, const int32_t* region_of_node, int region_nodes,
-                           int patch_elems);
+                           int patch_elems, const PatchLds& lds = PatchLds());
 
 }  // namespace ebe

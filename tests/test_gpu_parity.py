@@ -133,6 +133,36 @@ def test_predict_matches_oracle_on_identical_history(small, oracle_lib, it):
     sol.set_history(vh0, ring0, it0)
 
 
+def test_one_global_region(small, oracle_lib):
+    """One predictor region over the whole 8x8x8-cell mesh (4,913 nodes, cut into 10 node chunks whose
+    partial Grams the least-squares kernel sums): predict on an identical history and a 30-step
+    trajectory against the oracle with the same single region."""
+    from paper_2409_20380_amd import ebe
+    c = dict(small)
+    wl, m = c["wl"], c["model"]
+    c["regions"] = np.zeros(m.n3 // 3, np.int32)
+    say("one global region: predict and 30-step trajectory")
+    sol = ebe.Solver(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol)
+    sol.assemble(c["mesh"].coords, c["mesh"].conn, c["em"], c["mat"], c["fx"], c["regions"])
+    it = 25
+    vh, ring = _random_history(m, wl.s, it, 300, c["fx"])
+    sol.set_history(to_dev(vh), to_dev(ring), it)
+    xg, s_eff = sol.predict()
+    X, Y, q, se = history_columns(ring, it, wl.s)
+    assert s_eff == se == wl.s
+    expect = oracle_lib.ab4(wl.dt, vh[0], vh[1], vh[2], vh[3]) + oracle_lib.predict_regional(c["regions"], X, Y, q)
+    assert rel_max(to_host(xg), expect) < 1e-10
+    sol.reset()
+    U, its, res = _gpu_run(sol, c["wave"], 30)
+    Uref, _ = _oracle_run(c, oracle_lib, 1e-13, 30)
+    _, its8 = _oracle_run(c, oracle_lib, wl.tol, 30)
+    err = np.linalg.norm(U - Uref) / np.linalg.norm(Uref)
+    say("one global region: space-time rel L2", err, "iters", its.mean(), its8.mean())
+    assert err < TRAJ_TOL and (res < wl.tol).all()
+    assert np.abs(its - its8).max() <= 3
+    sol.close()
+
+
 def test_predict_exact_recovery_in_snapshot_span(small):
     """Query e^{n-1} built inside span(X) per region: the prediction is Y a exactly."""
     m, sol, wl = small["model"], small["sol"], small["wl"]

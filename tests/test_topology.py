@@ -41,14 +41,18 @@ def probe():
     shutil.rmtree(d, ignore_errors=True)
 
 
-def build(probe, wl, patch_elems=256):
+def build(probe, wl, patch_elems=256, lds=None):
     mesh, em, mat, fx, regions, _ = wl.build()
     a = lambda x, t: np.ascontiguousarray(x, dtype=t)
     P = lambda x: x.ctypes.data_as(C.c_void_p)
     xyz, conn, emm, matt = a(mesh.coords, np.float64), a(mesh.conn, np.int32), a(em, np.int32), a(mat, np.float64)
     fxx, reg = a(fx, np.uint8), a(regions, np.int32)
-    rc = probe.probe_build(C.c_int64(mesh.n_nodes), P(xyz), C.c_int64(len(conn)), P(conn), P(emm),
-                           C.c_int(len(matt)), P(matt), P(fxx), P(reg), C.c_int(512), C.c_int(patch_elems))
+    args = (C.c_int64(mesh.n_nodes), P(xyz), C.c_int64(len(conn)), P(conn), P(emm), C.c_int(len(matt)), P(matt),
+            P(fxx), P(reg), C.c_int(512), C.c_int(patch_elems))
+    if lds is None:
+        rc = probe.probe_build(*args)
+    else:
+        rc = probe.probe_build_lds(*args, *(C.c_int64(v) for v in lds))
     assert rc == 0
     sz = np.zeros(7, np.int64)
     probe.probe_sizes(P(sz))
@@ -166,3 +170,65 @@ def test_bank_spreading_reduces_conflicts(probe):
     assert spread, "no full patch"
     assert np.mean(spread) < 1.25, np.mean(spread)
     assert np.mean(spread) < np.mean(plain) - 0.5, (np.mean(spread), np.mean(plain))
+
+
+@pytest.mark.parametrize("sizes", [[512], [513], [1], [614, 614, 615], [4096, 100, 1024 * 512 + 7], [1081665]],
+                         ids=["512", "513", "1", "3x614", "mixed", "one_global"])
+def test_region_chunks(probe, sizes):
+    """The predictor's node chunks tile each region with consecutive ranges of near-equal length: at most
+    512 nodes each, unless the region needs more than 64 chunks, then 64 equal ones."""
+    rs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    P = lambda x: x.ctypes.data_as(C.c_void_p)
+    probe.probe_region_chunks.restype = C.c_int64
+    n = probe.probe_region_chunks(P(rs), C.c_int32(len(sizes)), C.c_int64(0), None, None, None)
+    cs, cr, rc = np.zeros(n + 1, np.int32), np.zeros(n, np.int32), np.zeros(len(sizes) + 1, np.int32)
+    assert probe.probe_region_chunks(P(rs), C.c_int32(len(sizes)), C.c_int64(n), P(cs), P(cr), P(rc)) == n
+    assert cs[0] == 0 and cs[-1] == rs[-1] and (np.diff(cs) > 0).all()
+    assert rc[0] == 0 and rc[-1] == n
+    for r, size in enumerate(sizes):
+        c0, c1 = rc[r], rc[r + 1]
+        assert cs[c0] == rs[r] and cs[c1] == rs[r + 1]
+        assert (cr[c0:c1] == r).all()
+        lens = np.diff(cs[c0:c1 + 1])
+        want = min(64, -(-size // 512))
+        assert c1 - c0 == want
+        assert lens.max() - lens.min() <= 1
+        if want < 64:
+            assert lens.max() <= 512
+
+
+# per node, per vertex node, fixed bytes: the FP64 element pass (four wave accumulators and one operand per
+# node, vertex coordinates, a two-row material table)
+LDS_COEF = (120, 24, 48)
+
+
+@pytest.mark.parametrize("budget", [81920, 40000, 20000])
+def test_patch_lds_budget(probe, budget):
+    """Patches close before their nodes would exceed the LDS budget; with a budget the natural 256-element
+    patches fit, nothing changes."""
+    per_node, per_vertex, fixed_b = LDS_COEF
+    free = build(probe, inputs.SMALL, 256)
+    t = build(probe, inputs.SMALL, 256, lds=(per_node, per_vertex, fixed_b, budget))
+    need = [fixed_b + per_node * (n1 - n0) + per_vertex * int(t["nv"][p]) for p, e0, e1, n0, n1 in patches(t)]
+    assert max(need) <= budget
+    counts = [e1 - e0 for p, e0, e1, n0, n1 in patches(t) if e1 > e0]
+    assert sum(counts) == len(t["conn"]) and max(counts) <= 256
+    natural = max(fixed_b + per_node * (n1 - n0) + per_vertex * int(free["nv"][p])
+                  for p, e0, e1, n0, n1 in patches(free))
+    if natural <= budget:
+        assert t["npat"] == free["npat"] and (t["el_ptr"] == free["el_ptr"]).all()
+    else:
+        assert t["npat"] > free["npat"]
+        # a patch is closed only when the next element would not fit
+        conn, i2u = t["conn"], t["i2u"]
+        for p, e0, e1, n0, n1 in patches(t):
+            if p + 1 >= t["npat"] or e1 - e0 == 256:
+                continue
+            ent = t["nodes"][n0:n1] & ~np.uint32(OWNER)
+            users = set(int(i2u[v]) for v in ent)
+            nxt = t["lids"][e1]   # local ids of the next patch's first element, in the next patch
+            m0, m1 = t["pn_ptr"][p + 1], t["pn_ptr"][p + 2]
+            nxt_users = [int(i2u[int(t["nodes"][m0 + int(l)] & ~np.uint32(OWNER))]) for l in nxt]
+            add = [u for u in nxt_users if u not in users]
+            add_v = sum(1 for i, u in enumerate(nxt_users) if u not in users and i < 4)
+            assert fixed_b + per_node * (n1 - n0 + len(add)) + per_vertex * (int(t["nv"][p]) + add_v) > budget

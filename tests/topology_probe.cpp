@@ -22,6 +22,21 @@ extern "C" int probe_build(int64_t nn, const double* xyz, int64_t ne, const int3
     return e.empty() ? 0 : 1;
 }
 
+// As probe_build, with the patch LDS budget of the element kernels.
+extern "C" int probe_build_lds(int64_t nn, const double* xyz, int64_t ne, const int32_t* conn, const int32_t* em,
+                               int nm, const double* mat, const uint8_t* fx, const int32_t* reg, int region_nodes,
+                               int patch_elems, int64_t per_node, int64_t per_vertex, int64_t fixed_bytes,
+                               int64_t budget) {
+    g_T = Topology();
+    PatchLds lds;
+    lds.per_node = per_node;
+    lds.per_vertex = per_vertex;
+    lds.fixed = fixed_bytes;
+    lds.budget = budget;
+    std::string e = build_topology(g_T, nn, xyz, ne, conn, em, nm, mat, fx, reg, region_nodes, patch_elems, lds);
+    return e.empty() ? 0 : 1;
+}
+
 // sizes: n_patches, n_patches_pad, PN (patch-node entries), E, max_pn, max_nv, n_slots
 extern "C" void probe_sizes(int64_t* out) {
     out[0] = g_T.n_patches;
@@ -44,4 +59,19 @@ extern "C" void probe_arrays(int32_t* el_ptr, int32_t* pn_ptr, int32_t* nv, uint
         for (int i = 0; i < 10; ++i) lids[10 * k + i] = g_T.elems[k].lid[i];
     std::memcpy(slot_ptr, g_T.slot_ptr.data(), g_T.slot_ptr.size() * 4);
     std::memcpy(i2u, g_T.i2u.data(), g_T.i2u.size() * 4);
+}
+
+// Node chunks of the predictor regions given by region_start [nr + 1]; returns
+// the number of chunks and fills chunk_start [C+1], chunk_region [C] and
+// region_chunk [nr+1] when cap (the room in chunk_region) is large enough.
+extern "C" int64_t probe_region_chunks(const int32_t* region_start, int32_t nr, int64_t cap, int32_t* chunk_start,
+                                       int32_t* chunk_region, int32_t* region_chunk) {
+    std::vector<int32_t> rs(region_start, region_start + nr + 1), cs, cr, rc;
+    region_chunks(rs, cs, cr, rc);
+    if ((int64_t)cr.size() <= cap) {
+        std::memcpy(chunk_start, cs.data(), cs.size() * 4);
+        std::memcpy(chunk_region, cr.data(), cr.size() * 4);
+        std::memcpy(region_chunk, rc.data(), rc.size() * 4);
+    }
+    return (int64_t)cr.size();
 }

@@ -111,8 +111,8 @@ def main():
     ap.add_argument("--inner-iters", type=int, default=0, help="inner PCG trips per outer trip (0: library default)")
     ap.add_argument("--inner-tol", type=float, default=0.0, help="inner relative tolerance (0: library default)")
     ap.add_argument("--drop-tol", type=float, default=0.0,
-                    help="predictor column drop threshold (0: 1e-6 for fp64, 1e-5 for the mixed forms, whose FP32 "
-                         "inner solves leave rounding noise in the snapshots)")
+                    help="predictor column drop threshold (0: the library's, 1e-6 for fp64 and 1e-5 for the mixed "
+                         "forms, whose FP32 inner solves leave rounding noise in the snapshots)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB device-to-device once (counter calibration)")
     args = ap.parse_args()
@@ -145,9 +145,9 @@ def main():
     dof = 3 * mesh.n_nodes
     log(f"mesh {wl.cells}: {mesh.n_nodes} nodes, {dof} dof, {mesh.n_elems} elements")
     aR, bR = wl.rayleigh
-    drop = args.drop_tol or (1e-6 if args.precision == "fp64" else 1e-5)
     sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems, precision=prec,
-                     inner_iters=args.inner_iters, inner_tol=args.inner_tol, drop_tol=drop)
+                     inner_iters=args.inner_iters, inner_tol=args.inner_tol, drop_tol=args.drop_tol)
+    drop = sol.effective_config().drop_tol
     t0 = time.time()
     sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
     sizes = sol.sizes()
@@ -304,7 +304,7 @@ def run_learned(args):
     # the two single-case growth forms together: the trained network's guess refined by the
     # flexible FP64 PCG with the FP32 inner solve, against the same FP32 refine with the plain guess
     solm = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems, precision=ebe.PREC_FP32,
-                      inner_iters=args.inner_iters, inner_tol=args.inner_tol, drop_tol=args.drop_tol or 1e-5)
+                      inner_iters=args.inner_iters, inner_tol=args.inner_tol, drop_tol=args.drop_tol)
     solm.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
     inner_trips = solm.effective_config().inner_iters
     mixed_plain = run(ebe.PRED_SNAPSHOT, test, None, solm)

@@ -91,7 +91,7 @@ typedef struct {
     double tol;             /* relative residual tolerance of Algorithm 1 (e.g. 1e-8) */
     double drop_tol;        /* snapshot column kept only if its part orthogonal to the
                                earlier kept columns has norm >= drop_tol * its norm
-                               (<= 0: 1e-6) */
+                               (<= 0: 1e-6, or 1e-5 with an FP32 / BF16 inner solve) */
     double inner_tol;       /* mixed precision: relative residual target of each inner
                                solve (<= 0: 1e-2) */
     int32_t max_iter;       /* PCG iteration cap per solve (<= 0: 10000) */

@@ -593,7 +593,9 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
         return EBE_E_INVALID_ARG;
     }
     if (c.max_iter <= 0) c.max_iter = 10000;
-    if (c.drop_tol <= 0) c.drop_tol = 1e-6;
+    // FP32 inner solves leave rounding noise of about 1e-5 of a snapshot's norm, which a
+    // smaller threshold would fit as signal
+    if (c.drop_tol <= 0) c.drop_tol = c.precision == EBE_PREC_FP64 ? 1e-6 : 1e-5;
     if (c.region_nodes <= 0) c.region_nodes = 512;
     if (c.patch_elems <= 0) c.patch_elems = kMaxPatchElems;
     if (c.inner_iters <= 0) c.inner_iters = 12;

@@ -181,7 +181,7 @@ class Solver:
     """One handle of the library: a mesh, its state and its history."""
 
     def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
-                 max_iter=10000, drop_tol=1e-6, region_nodes=512, patch_elems=256, chunk_iters=0, precision=PREC_FP64,
+                 max_iter=10000, drop_tol=0.0, region_nodes=512, patch_elems=256, chunk_iters=0, precision=PREC_FP64,
                  inner_iters=0, inner_tol=0.0, stream=None):
         import torch
         L = lib()

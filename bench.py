@@ -71,6 +71,16 @@ def cpu_baseline(wl, mesh, em, mat, fx, regions, wave, steps, gpu_iters=None):
     dt = time.time() - t0
     dof = 3 * mesh.n_nodes
     ms_it = dt / max(1, sum(iters)) * 1e3
+    # the oracle's BCSR product alone: 3x3 FP64 block + int32 column per stored block, int64 row
+    # pointer, x and y once per block row
+    nnzb = int(oracle.lib().orc_nnzb(model._h))
+    spmv_bytes = nnzb * (72 + 4) + mesh.n_nodes * (8 + 24 + 24)
+    p = np.ones(dof)
+    model.spmv("A", p)
+    t1 = time.time()
+    for _ in range(5):
+        model.spmv("A", p)
+    spmv_s = (time.time() - t1) / 5
     note = ""
     if gpu_iters:
         # the same oracle at the timed steps' iteration count (the steps from rest need more trips)
@@ -83,6 +93,9 @@ def cpu_baseline(wl, mesh, em, mat, fx, regions, wave, steps, gpu_iters=None):
         "kind": "oracle",
         "sample": (f"steps 1-{steps} of the same workload from rest ({np.mean(iters):.0f} PCG iterations/step, "
                    f"{ms_it:.0f} ms per iteration; BCSR assembly of {t_asm:.0f} s excluded); {dt:.1f} s wall{note}"),
+        "iters_per_step": float(np.mean(iters)),
+        "spmv_gbs": spmv_bytes / spmv_s / 1e9,
+        "spmv_ms": spmv_s * 1e3,
     }
 
 

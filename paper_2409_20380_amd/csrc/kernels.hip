@@ -308,19 +308,26 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
 
 // Persistent grid of the apply / right-hand-side passes: the workgroups that
 // fit on the device at once (one or two per CU by LDS), a multiple of 8.
+// CU count and LDS bytes per CU of the current device, queried once per process
+// (a function-local static: initialised once, also under concurrent first calls).
 static void device_limits(int& cus, int& lds_cu) {
-    static int c = 0, l = 0;
-    if (!c) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipDeviceGetAttribute(&l, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess) {
-            c = 256;
-            l = 160 * 1024;
+    struct Limits {
+        int cus = 256, lds = 160 * 1024;
+    };
+    static const Limits L = [] {
+        Limits v;
+        int dev = 0, c = 0, l = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            hipDeviceGetAttribute(&l, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess &&
+            c > 0 && l > 0) {
+            v.cus = c;
+            v.lds = l;
         }
-    }
-    cus = c;
-    lds_cu = l;
+        return v;
+    }();
+    cus = L.cus;
+    lds_cu = L.lds;
 }
 
 // The patch builder's LDS limit: the element pass of the PCG loop keeps two

@@ -99,7 +99,9 @@ typedef struct {
     int32_t predictor;      /* EBE_PRED_* */
     int32_t region_nodes;   /* nodes per predictor region when ebe_assemble receives no
                                region map (<= 0: 512) */
-    int32_t patch_elems;    /* elements per EBE patch, 1..256 (<= 0: 256) */
+    int32_t patch_elems;    /* at most this many elements per EBE patch, 1..256 (<= 0: 256);
+                               a patch closes earlier when its nodes would need more
+                               LDS than two resident element workgroups per CU allow */
     int32_t chunk_iters;    /* PCG iterations enqueued between convergence checks
                                (<= 0: adaptive) */
     int32_t precision;      /* EBE_PREC_*: how Algorithm 1 is run (see below) */
@@ -159,9 +161,10 @@ const char* ebe_last_error(const ebe_handle* h);
  *   mat     host [n_mat][3] density rho, P velocity vp, S velocity vs;
  *           mu = rho vs^2, lambda = rho (vp^2 - 2 vs^2)
  *   fixed   host [n_nodes][3] 1 = component fixed (zero displacement)
- *   region_of_node host [n_nodes] predictor region id in [0, R), or NULL to
- *           let the library group nodes into spatially compact regions of
- *           cfg.region_nodes nodes (query them with ebe_get_regions)
+ *   region_of_node host [n_nodes] predictor region id in [0, R), every id
+ *           used, any region size (one region over the whole mesh is valid),
+ *           or NULL to let the library group nodes into spatially compact
+ *           regions of cfg.region_nodes nodes (query them with ebe_get_regions)
  * Builds the element patches, the internal node order, the element
  * geometry checks and the block-Jacobi inverse, and resets the state to rest
  * (u = v = a = 0, empty history, step 0).

@@ -282,3 +282,39 @@ def test_full_size_inference_sampled_rows():
     say(f"sampled rows: rel error vs BF16-input oracle {e:.2e}")
     assert e < INFER_MIMIC_TOL
     sol.close()
+
+
+def test_trained_network_generalises(oracle_lib):
+    """What training gains: on a wave the network never saw, its estimate of the
+    AB4 error has a loss well below that of the zero network (no correction,
+    i.e. the AB4 guess alone), after training on trajectories the solver
+    generated itself with the library's own kernels."""
+    torch = pytest.importorskip("torch")
+    from paper_2409_20380_amd import learn
+    wl = inputs.Workload(SMALL.name, cells=SMALL.cells, nt=60, s=SMALL.s)
+    say("train on 4 small-mesh trajectories, evaluate on a held-out wave")
+    c = build_case(wl, oracle_lib)
+    sol = c["sol"]
+    try:
+        nodes = torch.from_numpy(inputs.sample_nodes(3, c["fx"], 1024)).cuda()
+        train_seeds = inputs.LEARN_TRAIN_SEEDS[:4]
+        learn.generate(sol, wl, train_seeds, 60, nodes, len(train_seeds) * 56 * nodes.numel())
+        losses = learn.train(sol, 1, [(1000, 1e-3), (500, 3e-4)], 1024)
+        trained, scales = sol.mlp_get()
+        # held-out samples (a different capacity drops the training samples)
+        learn.generate(sol, wl, inputs.LEARN_TEST_SEEDS[:1], 60, nodes, 56 * nodes.numel())
+        raw = sol.samples()
+        pick = torch.from_numpy(inputs.minibatches(9, 1, 8192, raw.shape[0])[0]).cuda()
+        raw = raw[pick]
+        div = torch.tensor([scales[0]] * 3 + [scales[1]] * 9 + [scales[2]] * 3, device="cuda")
+        X = (raw[:, :15] / div).contiguous()
+        T = (raw[:, 15:] / float(scales[3])).contiguous()
+        _, l_trained = sol.mlp_grad(X, T)
+        sol.mlp_set(np.zeros_like(trained), scales)
+        _, l_zero = sol.mlp_grad(X, T)
+        say(f"training loss {losses[:20].mean():.3f} -> {losses[-50:].mean():.3f}; "
+            f"held-out loss trained {l_trained:.3f} vs zero network {l_zero:.3f}")
+        assert losses[-50:].mean() < 0.7 * losses[:20].mean()
+        assert l_trained < 0.7 * l_zero
+    finally:
+        sol.close()

@@ -106,7 +106,7 @@ typedef struct {
                                (<= 0: adaptive) */
     int32_t precision;      /* EBE_PREC_*: how Algorithm 1 is run (see below) */
     int32_t inner_iters;    /* mixed precision: inner PCG trips per outer trip at most
-                               (<= 0: 12) */
+                               (<= 0: 16) */
     int32_t reserved[4];
 } ebe_config;
 

@@ -598,7 +598,7 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     if (c.drop_tol <= 0) c.drop_tol = c.precision == EBE_PREC_FP64 ? 1e-6 : 1e-5;
     if (c.region_nodes <= 0) c.region_nodes = 512;
     if (c.patch_elems <= 0) c.patch_elems = kMaxPatchElems;
-    if (c.inner_iters <= 0) c.inner_iters = 12;
+    if (c.inner_iters <= 0) c.inner_iters = 16;
     if (c.inner_tol <= 0) c.inner_tol = 1e-2;
     ebe_handle* h = new (std::nothrow) ebe_handle();
     if (!h) {

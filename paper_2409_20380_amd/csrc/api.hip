@@ -388,7 +388,9 @@ int solve_mixed(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) 
             launch_outer_z(s, h->dn, h->e_in, h->r, h->r_prev, h->z, h->sc, slot(j), j);
             double* pprev = h->p[h->par];
             double* pcur = h->p[h->par ^ 1];
-            bool timed = h->timing_every > 0 && (h->pcg_launches % h->timing_every) == 0 && j + 2 < h->last_iters;
+            // the first outer trip always works; later ones well before the previous solve's count
+            bool timed = h->timing_every > 0 && (h->pcg_launches % h->timing_every) == 0 &&
+                         (j == 0 || j + 2 < h->last_iters);
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timed) {
                 e0 = take_event(h);

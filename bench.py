@@ -104,7 +104,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=250, help="timed time steps")
     ap.add_argument("--warmup", type=int, default=250, help="untimed time steps before the timed ones")
-    ap.add_argument("--timing-every", type=int, default=8, help="bracket every n-th matvec launch with events")
+    ap.add_argument("--timing-every", type=int, default=32, help="bracket every n-th matvec launch with events")
     ap.add_argument("--cpu-steps", type=int, default=6, help="oracle steps in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "ebe_pcg_traffic.txt"))

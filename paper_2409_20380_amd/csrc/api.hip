@@ -301,7 +301,7 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
     h->q_ready = false;
     launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(0), 0);
     check_launch();
-    int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters - 2);
+    int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters + 1);
     int done = DONE_RUNNING;
     int j = 0;
     for (int round = 0;; ++round) {

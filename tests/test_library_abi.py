@@ -43,3 +43,25 @@ def test_create_rejects_bad_config_without_touching_a_device():
     assert L.ebe_create(ctypes.byref(cfg), None, ctypes.byref(h)) == ebe.E_INVALID_ARG
     assert b"invalid configuration" in L.ebe_last_error(None)
     assert L.ebe_destroy(None) == ebe.OK
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No CPU fallback: with the library missing, the first call into the binding raises."""
+    from paper_2409_20380_amd import ebe
+    monkeypatch.setattr(ebe, "_lib", None)
+    monkeypatch.setattr(ebe, "LIB_PATH", os.path.join(os.path.dirname(ebe.LIB_PATH), "missing_libebe.so"))
+    with pytest.raises(ImportError):
+        ebe.lib()
+    with pytest.raises(ImportError):
+        ebe.Solver(0.01)
+
+
+def test_product_code_does_not_use_the_oracle():
+    """Only the tests, smoke() and the bench's CPU-baseline leg may touch oracle/: the package imports none of it."""
+    pkg = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2409_20380_amd")
+    for root, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(root, f), encoding="utf-8").read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "oracle.c" not in text and "liboracle" not in text, f

@@ -70,6 +70,11 @@ struct ebe_handle {
     double *t0 = nullptr, *t1 = nullptr, *coef = nullptr, *gh = nullptr;
     int par = 0;
     int last_iters = 0;
+    // Set by ebe_step for the duration of its solve: the Newmark update is
+    // enqueued, guarded by the stop flag, behind every read-back of the scalars,
+    // so that it runs while the host handles the read-back.
+    bool post_newmark = false;
+    double* post_slot = nullptr;
     DevScalars* sc = nullptr;
     DevScalars* sc_host = nullptr;
     double* pap_part = nullptr;   // (p, A p) partials of the matvec grid
@@ -256,6 +261,24 @@ void sync_stream(ebe_handle* h) {
     if (!h->ev_pending.empty()) harvest_timing(h, true);
 }
 
+// Copies the scalars to the host and waits for them.  With post_newmark the
+// guarded Newmark update goes behind the copy and is not waited for.
+void read_scalars(ebe_handle* h) {
+    hipStream_t s = h->stream;
+    HIPCHK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    if (!h->post_newmark) {
+        sync_stream(h);
+        return;
+    }
+    hipEvent_t e = take_event(h);
+    HIPCHK(hipEventRecord(e, s));
+    launch_newmark(s, h->n3(), h->cfg.dt, h->x, h->dab, h->u, h->vslot(0), h->vslot(3), h->a, h->post_slot, h->sc);
+    check_launch();
+    HIPCHK(hipEventSynchronize(e));
+    h->ev_free.push_back(e);
+    if (!h->ev_pending.empty()) harvest_timing(h, true);
+}
+
 // Statistics and status of a finished solve from the scalars read back last.
 int finish_solve(ebe_handle* h, double* x, int done, ebe_solve_stats* st) {
     const DevScalars& S = *h->sc_host;
@@ -334,8 +357,7 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
         launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(j), 1);
         launch_check_finalize(s, h->sc, slot(j), g_res, j, tol);
         check_launch();
-        HIPCHK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-        sync_stream(h);
+        read_scalars(h);
         done = h->sc_host->done;
         if (done == DONE_RUNNING) {
             chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters / 8);
@@ -413,8 +435,7 @@ int solve_mixed(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) 
         launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(j), 1);
         launch_check_finalize(s, h->sc, slot(j), g_res, j, tol);
         check_launch();
-        HIPCHK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-        sync_stream(h);
+        read_scalars(h);
         done = h->sc_host->done;
         if (done == DONE_RUNNING) {
             chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : 1;
@@ -864,8 +885,20 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
         if (collect) launch_collect_pre(s, h->coll_nodes, h->coll_k, h->dab, h->coll_stage);
         const bool learned = learned_due(h, n) && (h->cand_losses < kCandPatience || n % kCandProbe == 0);
         if (learned) choose_learned(h, f_int, base_acc);
+        double* slot = h->cfg.s >= 1 ? h->ring_slot((n - 1) % (h->cfg.s + 1)) : nullptr;
         ebe_solve_stats st{};
-        int rc = run_solve(h, h->b, h->x, &st);
+        // without sample collection (which reads the state before the update) the
+        // Newmark update is enqueued during the solve, guarded by the stop flag
+        h->post_newmark = !collect;
+        h->post_slot = slot;
+        int rc;
+        try {
+            rc = run_solve(h, h->b, h->x, &st);
+        } catch (...) {
+            h->post_newmark = false;
+            throw;
+        }
+        h->post_newmark = false;
         if (rc < 0) return rc;
         if (learned) h->cand_losses = h->sc_host->cand_pick ? 0 : h->cand_losses + 1;
         if (collect) {
@@ -874,8 +907,9 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
                                 h->samples + h->samples_n * kMlpSample);
             h->samples_n += h->coll_k;
         }
-        double* slot = h->cfg.s >= 1 ? h->ring_slot((n - 1) % (h->cfg.s + 1)) : nullptr;
-        launch_newmark(s, h->n3(), h->cfg.dt, h->x, h->dab, h->u, h->vslot(0), h->vslot(3), h->a, slot);
+        const int done = h->sc_host->done;
+        const bool updated = !collect && (done == DONE_CONVERGED || done == DONE_MAXITER);
+        if (!updated) launch_newmark(s, h->n3(), h->cfg.dt, h->x, h->dab, h->u, h->vslot(0), h->vslot(3), h->a, slot);
         check_launch();
         h->head = (h->head + 3) & 3;
         h->it = n;

@@ -165,8 +165,10 @@ void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChun
                        double* coef);
 void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, const double* coef,
                        const double* dab, double* x);
+// guard (may be NULL): run only once the solve's stop flag reads converged or max_iter
 void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, const double* dab, double* u,
-                    const double* v_old, double* v_new, double* a, double* ring_slot);
+                    const double* v_old, double* v_new, double* a, double* ring_slot,
+                    const DevScalars* guard = nullptr);
 void launch_gather3(hipStream_t s, int64_t n, const int32_t* idx, const double* in, double* out);
 void launch_zero(hipStream_t s, int64_t count, double* p);
 

@@ -1328,8 +1328,14 @@ void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, const DevChun
 
 // Newmark-beta (beta = 1/4, gamma = 1/2): u += du; v' = -v + (2/dt) du;
 // a' = -a - (4/dt) v + (4/dt^2) du; AB error du - dab into the ring slot.
+// With a guard, the update runs only if the solve that produced du has ended
+// with a usable increment (converged, or stopped at max_iter).
 __global__ void k_newmark(int64_t n3, double dt, const double* du, const double* dab, double* u, const double* v_old,
-                          double* v_new, double* a, double* ring_slot) {
+                          double* v_new, double* a, double* ring_slot, const DevScalars* guard) {
+    if (guard) {
+        const int d = guard->done;
+        if (d != DONE_CONVERGED && d != DONE_MAXITER) return;
+    }
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n3) return;
     double d = du[i], vo = v_old[i];
@@ -1340,9 +1346,9 @@ __global__ void k_newmark(int64_t n3, double dt, const double* du, const double*
 }
 
 void launch_newmark(hipStream_t s, int64_t n3, double dt, const double* du, const double* dab, double* u,
-                    const double* v_old, double* v_new, double* a, double* ring_slot) {
+                    const double* v_old, double* v_new, double* a, double* ring_slot, const DevScalars* guard) {
     int nb = (int)((n3 + 255) / 256);
-    hipLaunchKernelGGL(k_newmark, dim3(nb), dim3(256), 0, s, n3, dt, du, dab, u, v_old, v_new, a, ring_slot);
+    hipLaunchKernelGGL(k_newmark, dim3(nb), dim3(256), 0, s, n3, dt, du, dab, u, v_old, v_new, a, ring_slot, guard);
 }
 
 __global__ void k_gather3(int64_t n, const int32_t* idx, const double* in, double* out) {

@@ -389,7 +389,9 @@ int solve_mixed(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) 
     h->q_ready = false;
     launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(0), 0);
     check_launch();
-    int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(1, h->last_iters - 1);
+    // an outer trip past the stop test still launches its ~2 x inner_iters guarded kernels, so the
+    // first chunk is the previous count (not more), which covers almost every step in one read-back
+    int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(1, h->last_iters);
     int done = DONE_RUNNING;
     int j = 0;
     for (int round = 0;; ++round) {

@@ -81,6 +81,28 @@ def cpu_baseline(wl, mesh, em, mat, fx, regions, wave, steps, gpu_iters=None):
     for _ in range(5):
         model.spmv("A", p)
     spmv_s = (time.time() - t1) / 5
+    # PCG iterations alone (no right-hand side or predictor), on all threads and on one core
+    rhs = np.random.default_rng(7).standard_normal(dof)
+    rhs[np.asarray(fx).reshape(-1) != 0] = 0.0
+
+    def pcg_ms(k):
+        t = time.time()
+        _, s_ = model.pcg(rhs, np.zeros(dof), tol=1e-30, max_iter=k)
+        return (time.time() - t) / max(1, s_.iters) * 1e3
+
+    n_thr = oracle.num_threads()
+    pcg_all = pcg_ms(20)
+    oracle.set_threads(1)
+    try:
+        pcg_one = pcg_ms(4)
+    finally:
+        oracle.set_threads(n_thr)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     note = ""
     if gpu_iters:
         # the same oracle at the timed steps' iteration count (the steps from rest need more trips)
@@ -96,6 +118,9 @@ def cpu_baseline(wl, mesh, em, mat, fx, regions, wave, steps, gpu_iters=None):
         "iters_per_step": float(np.mean(iters)),
         "spmv_gbs": spmv_bytes / spmv_s / 1e9,
         "spmv_ms": spmv_s * 1e3,
+        "pcg_ms_per_iteration": {"all_threads": pcg_all, "one_core": pcg_one},
+        "one_core_rate_at_gpu_iters": (dof / (gpu_iters * pcg_one * 1e-3)) if gpu_iters else None,
+        "host": {"cpu_model": cpu_model, "cpus_visible": os.cpu_count(), "threads_used": n_thr},
     }
 
 

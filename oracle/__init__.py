@@ -88,6 +88,7 @@ def lib():
                                C.POINTER(d_p), C.POINTER(d_p), C.POINTER(C.c_int32), d_p, d_p, d_p, d_p,
                                C.POINTER(StepStats)]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -109,6 +110,11 @@ def element_matrices(xv, lam, mu, rho):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 class Model:

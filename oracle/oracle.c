@@ -728,3 +728,13 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Thread count of later parallel loops (timing; the dot products' reduction order, and so their
+ * rounding, follows the thread count). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

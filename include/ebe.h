@@ -212,7 +212,9 @@ int ebe_refine(ebe_handle* h, const double* b, double* x, ebe_solve_stats* stats
 /* One time step: right-hand side, predictor, Algorithm 1, Newmark-beta
  * (beta = 1/4, gamma = 1/2) update of u, v, a, velocity history and snapshot
  * ring.  f_ext (device) and base_acc (host [3]) as in ebe_rhs, at the new time.
- * stats may be NULL (then the call does not synchronise). */
+ * The call waits for the solve's stop test (the scalars are read back once
+ * per chunk of trips); the final update may still be running on the handle's
+ * stream when it returns, ordered before any later call.  stats may be NULL. */
 int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_step_stats* stats);
 
 /* Checkpoint / resume.  u, v, a: device [3N] each, caller order.

@@ -623,33 +623,64 @@ typedef struct {
     double dt, aR, bR, tol, drop;
     int32_t max_iter, s, kind; /* kind: 0 zero guess, 1 AB4, 2 AB4 + regional snapshots */
     int32_t want_ab_residual;
+    int32_t s_min;             /* kind 2: the map needs at least this many column pairs (<= 0: 1) */
+    int32_t guard;             /* kind 2: keep the AB4 guess when its initial residual is smaller,
+                                  and restart the snapshot window (see orc_step) */
 } orc_params;
 
 typedef struct {
     int32_t it;          /* index of the step just solved */
-    int32_t s_eff;
+    int32_t s_eff;       /* column pairs of the map used (0: no map) */
     int32_t iters;
     int32_t status;
-    double res_ab;       /* initial relative residual of the AB4 guess (if requested) */
+    int32_t pick;        /* guard: 1 map kept, 0 AB4 kept (window restarted); -1 no comparison */
+    int32_t first;       /* the window used held e^first .. e^{it-1} (0: no map) */
+    double res_ab;       /* initial relative residual of the AB4 guess (guard or if requested) */
+    double res_map;      /* initial relative residual of the map's guess (guard only) */
     double res0;         /* initial relative residual of the guess actually used */
     double res_rec, res_true, fnorm;
 } orc_step_stats;
+
+/* Relative residual ||b - A x|| / ||b|| (0 when b = 0). */
+static double rel_residual(const orc_model* m, const double* b, const double* x, double* tmp) {
+    int64_t n3 = 3 * m->n;
+    orc_spmv(m, 2, x, tmp);
+    double s = 0.0;
+    for (int64_t i = 0; i < n3; ++i) s += (b[i] - tmp[i]) * (b[i] - tmp[i]);
+    double fn = sqrt(dot(n3, b, b));
+    return fn > 0 ? sqrt(s) / fn : sqrt(s);
+}
 
 /* State arrays (all length 3N, owned by the caller):
  *   u, v, a                    displacement, velocity, acceleration at step it
  *   vh[0..3]                   v^{it}, v^{it-1}, v^{it-2}, v^{it-3}  (v^{j<=0} = 0)
  *   ring[0..s]                 AB errors e^j = du^j - du_AB^j, e^j stored in
  *                              slot (j-1) mod (s+1)
+ *   *win                       first step whose AB error may enter the
+ *                              snapshot window (1 at rest; may be NULL = 1)
  * *it is the number of completed steps; this call advances it by one.
  * g: base acceleration at the new time (3 values, may be NULL); f_add: extra
- * nodal force at the new time (may be NULL).  du_out, guess_out optional. */
+ * nodal force at the new time (may be NULL).  du_out, guess_out optional.
+ *
+ * Guess of step n = it + 1 (kind 2; Sec. 3.2): the AB4 increment plus the
+ * regional map fitted on the window of AB errors e^first .. e^{n-1}, with
+ * first = max(win, n - 1 - s): inputs X = e^first .. e^{n-2}, outputs
+ * Y = e^{first+1} .. e^{n-1} (one step later), query e^{n-1}; s_eff = n-1-first
+ * column pairs, and the map is used only when s_eff >= s_min (the paper draws
+ * s from [8, 32]).  With the guard, the AB4 guess is evaluated too and kept
+ * when its residual ||b - A x|| is strictly smaller; the window then restarts
+ * at this step (win = n): the map's columns up to e^{n-1} are discarded, so a
+ * window that spans a change of regime (the start from rest, a kink in the
+ * input) is not fitted again. */
 int orc_step(const orc_model* m, const orc_params* P, const int32_t* region_of_node, int32_t n_regions,
              double* u, double* v, double* a, double* const* vh, double* const* ring, int32_t* it,
-             const double* g, const double* f_add, double* du_out, double* guess_out, orc_step_stats* st) {
+             int32_t* win, const double* g, const double* f_add, double* du_out, double* guess_out,
+             orc_step_stats* st) {
     int64_t n3 = 3 * m->n;
     int n = *it + 1; /* new step index */
     memset(st, 0, sizeof(*st));
     st->it = n;
+    st->pick = -1;
     double* b = (double*)malloc(sizeof(double) * n3);
     double* dab = (double*)malloc(sizeof(double) * n3);
     double* x = (double*)malloc(sizeof(double) * n3);
@@ -658,35 +689,52 @@ int orc_step(const orc_model* m, const orc_params* P, const int32_t* region_of_n
     orc_ab4(n3, P->dt, vh[0], vh[1], vh[2], vh[3], dab);
     memcpy(x, dab, sizeof(double) * n3);
     if (P->kind == 0) memset(x, 0, sizeof(double) * n3);
-    int s_eff = P->s < n - 2 ? P->s : n - 2;
-    if (P->kind == 2 && s_eff >= 1) {
+    for (int64_t i = 0; i < n3; ++i)
+        if (m->fixed[i]) x[i] = 0.0;
+    int w = win ? *win : 1;
+    if (w < 1) w = 1;
+    int first = n - 1 - P->s;
+    if (first < w) first = w;
+    int s_eff = n - 1 - first;
+    int s_min = P->s_min < 1 ? 1 : (P->s_min < P->s ? P->s_min : P->s);
+    double* tmp = (double*)malloc(sizeof(double) * n3);
+    if (P->kind == 2 && P->s >= 1 && s_eff >= s_min) {
         const double** X = (const double**)malloc(sizeof(double*) * s_eff);
         const double** Y = (const double**)malloc(sizeof(double*) * s_eff);
         int S1 = P->s + 1;
         for (int j = 0; j < s_eff; ++j) {
-            int jx = n - s_eff - 1 + j; /* inputs e^{n-s_eff-1} .. e^{n-2} */
-            X[j] = ring[(jx - 1) % S1];
-            Y[j] = ring[jx % S1];       /* outputs e^{n-s_eff} .. e^{n-1} */
+            X[j] = ring[(first + j - 1) % S1]; /* e^{first+j}   */
+            Y[j] = ring[(first + j) % S1];     /* e^{first+j+1} */
         }
         const double* q = ring[(n - 2) % S1]; /* query e^{n-1} */
-        double* ehat = (double*)calloc(n3, sizeof(double));
-        orc_predict_regional(m->n, region_of_node, n_regions, s_eff, X, Y, q, P->drop, ehat);
-        for (int64_t i = 0; i < n3; ++i) x[i] += ehat[i];
-        free(ehat); free(X); free(Y);
+        double* xm = (double*)calloc(n3, sizeof(double));
+        orc_predict_regional(m->n, region_of_node, n_regions, s_eff, X, Y, q, P->drop, xm);
+        for (int64_t i = 0; i < n3; ++i) xm[i] = m->fixed[i] ? 0.0 : x[i] + xm[i];
         st->s_eff = s_eff;
+        st->first = first;
+        if (P->guard) {
+            st->res_ab = rel_residual(m, b, x, tmp);
+            st->res_map = rel_residual(m, b, xm, tmp);
+            if (st->res_ab < st->res_map) {
+                st->pick = 0;
+                if (win) *win = n;
+            } else {
+                st->pick = 1;
+                memcpy(x, xm, sizeof(double) * n3);
+            }
+        } else {
+            memcpy(x, xm, sizeof(double) * n3);
+        }
+        free(xm); free(X); free(Y);
     }
-    for (int64_t i = 0; i < n3; ++i)
-        if (m->fixed[i]) x[i] = 0.0;
     if (guess_out) memcpy(guess_out, x, sizeof(double) * n3);
-    if (P->want_ab_residual) {
-        double* q = (double*)malloc(sizeof(double) * n3);
-        double fn = sqrt(dot(n3, b, b));
-        orc_spmv(m, 2, dab, q);
-        double s = 0.0;
-        for (int64_t i = 0; i < n3; ++i) s += (b[i] - q[i]) * (b[i] - q[i]);
-        st->res_ab = fn > 0 ? sqrt(s) / fn : 0.0;
-        free(q);
+    if (P->want_ab_residual && st->pick < 0) {
+        double* xab = (double*)malloc(sizeof(double) * n3);
+        for (int64_t i = 0; i < n3; ++i) xab[i] = m->fixed[i] ? 0.0 : dab[i];
+        st->res_ab = rel_residual(m, b, xab, tmp);
+        free(xab);
     }
+    free(tmp);
     orc_solve_stats ss;
     int status = orc_pcg(m, b, x, P->tol, P->max_iter, &ss);
     st->iters = ss.iters;

@@ -494,3 +494,145 @@ def test_predictor_does_not_change_the_answer_only_the_iterations(oracle_lib):
     tail = slice(20, None)
     assert runs[1][1][tail].mean() < runs[0][1][tail].mean()
     assert runs[2][1][tail].mean() < runs[1][1][tail].mean()
+
+
+# ----------------------------------------------------------------------------
+# P8 in the time loop: which AB errors form the snapshot window of a step
+# ----------------------------------------------------------------------------
+def _window_case(oracle_lib, seed, s, it, win):
+    """A stepper about to take step n = it + 1 whose ring holds, per region R,
+    AB errors e^k = B_R z^k: inside the window the coefficients follow
+    z^{k+1} = Q_R z^k (an exact one-step linear recurrence of dimension d =
+    s_eff), every other slot holds unrelated vectors of the same span.  The
+    map of Sec. 3.2 fitted on the right window then predicts e^n = B_R Q_R
+    z^{n-1} exactly, and any other choice of inputs, outputs or query does not.
+    Returns the stepper, the dofs' regions, the expected AB-error estimate and
+    the window's first step."""
+    mesh = inputs.box_mesh(4, 4, 4)
+    em, mat = inputs.two_layer_materials(mesh)
+    fx = inputs.fixed_bottom(mesh)
+    dt = 0.01
+    mod = oracle_lib.Model(mesh.coords, mesh.conn, em, mat, fx, 4 / dt ** 2, 1.0)
+    regions = inputs.block_regions(mesh, 4)
+    st = oracle_lib.Stepper(mod, dt, 0.0, 0.0, s=s, kind=2, tol=1e-8, regions=regions, s_min=1, guard=False)
+    n = it + 1
+    first = max(win, n - 1 - s)
+    d = n - 1 - first
+    rng = np.random.default_rng(seed)
+    free = fx.ravel() == 0
+    dof_region = np.repeat(regions, 3)
+    cols = {}                                      # step k -> e^k
+    expect = np.zeros(mod.n3)
+    steps_in_ring = range(max(1, n - 1 - s), n)    # the s + 1 newest steps occupy every slot
+    for k in steps_in_ring:
+        cols[k] = np.zeros(mod.n3)
+    for r in range(int(regions.max()) + 1):
+        sel = np.where((dof_region == r) & free)[0]
+        B = rng.standard_normal((sel.size, d))
+        Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+        z = rng.standard_normal(d)
+        zs = {}
+        for k in range(first, n):
+            zs[k] = z
+            z = Q @ z
+        Z = np.stack([zs[k] for k in range(first, n - 1)], axis=1)
+        assert np.linalg.cond(Z) < 1e4
+        for k in steps_in_ring:
+            c = zs[k] if k in zs else rng.standard_normal(d)
+            cols[k][sel] = B @ c
+        expect[sel] = B @ (Q @ zs[n - 1])
+    S1 = s + 1
+    for k, c in cols.items():
+        st.ring[(k - 1) % S1][:] = c
+    # slots of a ring that has not wrapped yet hold unrelated vectors too
+    for k in range(1, S1 + 1):
+        if k not in cols and n - 1 < S1:
+            st.ring[(k - 1) % S1][:] = 0.0
+            st.ring[(k - 1) % S1][free] = rng.standard_normal(free.sum())
+    for j in range(4):
+        st.vh[j][:] = 0.0
+        st.vh[j][free] = 1e-3 * rng.standard_normal(free.sum())
+    st.it.value = it
+    st.win.value = win
+    return st, free, expect, first
+
+
+@pytest.mark.parametrize("s,it,win", [
+    (8, 5, 1),     # ring not full: s_eff = 4 < s
+    (6, 7, 1),     # ring just full, not wrapped: s_eff = s
+    (6, 20, 1),    # ring wrapped twice
+    (8, 29, 25),   # window restarted at step 25: older valid-looking columns ignored
+])
+def test_snapshot_window_recovers_exact_recurrence(oracle_lib, s, it, win):
+    st, free, expect, first = _window_case(oracle_lib, 11 + it, s, it, win)
+    n = it + 1
+    vh0 = [c.copy() for c in st.vh]
+    ring0 = [c.copy() for c in st.ring]
+    dab = oracle_lib.ab4(st.P.dt, *vh0)
+    rec, du, guess = st.step(want_du=True, want_guess=True)
+    assert rec.s_eff == n - 1 - first and rec.first == first
+    ehat = guess - dab
+    assert not guess[~free].any()
+    err = np.abs(ehat[free] - expect[free]).max() / np.abs(expect).max()
+    assert err < 1e-10, err
+    # e^n = du - du_AB lands in slot (n - 1) mod (s + 1); the other slots are untouched
+    S1 = s + 1
+    for k in range(S1):
+        if k == (n - 1) % S1:
+            np.testing.assert_array_equal(st.ring[k], du - dab)
+        else:
+            np.testing.assert_array_equal(st.ring[k], ring0[k])
+    assert st.it.value == n and st.win.value == win
+
+
+def test_guard_keeps_ab4_and_restarts_the_window(oracle_lib):
+    # a ring of unrelated columns: the map's guess is far worse than AB4's
+    st, free, expect, first = _window_case(oracle_lib, 5, 8, 29, 1)
+    st.P.guard = 1
+    n = 30
+    dab = oracle_lib.ab4(st.P.dt, *[c.copy() for c in st.vh])
+    for k in range(len(st.ring)):
+        st.ring[k][free] = np.random.default_rng(k).standard_normal(free.sum())
+    rec, du, guess = st.step(want_guess=True)
+    xab = np.where(free, dab, 0.0)
+    assert rec.pick == 0 and rec.res_ab < rec.res_map
+    np.testing.assert_array_equal(guess, xab)
+    assert st.win.value == n
+    # the next step has no columns left: AB4 alone, no comparison
+    rec2, _, guess2 = st.step(want_guess=True)
+    assert rec2.s_eff == 0 and rec2.pick == -1 and st.win.value == n
+
+
+def test_guard_keeps_a_map_that_reproduces_the_solution(oracle_lib):
+    # window e^{n-2} = e^{n-1} = e*, the exact AB error of the step: the map with
+    # one column pair predicts e* itself, the guess solves the system
+    st, free, _, _ = _window_case(oracle_lib, 6, 4, 9, 1)
+    st.P.guard = 1
+    n = 10
+    g = np.array([0.3, -0.2, 0.5])
+    st.u[free] = 1e-4 * np.random.default_rng(1).standard_normal(free.sum())
+    b = st.m.rhs(st.u, st.v, st.a, st.P.dt, 0.0, 0.0, g=g)
+    du_star, _ = st.m.pcg(b, np.zeros(st.m.n3), tol=1e-14)
+    dab = oracle_lib.ab4(st.P.dt, *[c.copy() for c in st.vh])
+    e_star = np.where(free, du_star - dab, 0.0)
+    st.P.s_min = 1
+    st.win.value = n - 2            # window e^{n-2}, e^{n-1}: one column pair
+    for k in (n - 2, n - 1):
+        st.ring[(k - 1) % 5][:] = e_star
+    rec, _, guess = st.step(g=g, want_guess=True)
+    assert rec.s_eff == 1 and rec.pick == 1 and rec.res_map < 1e-10 < rec.res_ab
+    assert np.abs(guess - du_star).max() <= 1e-9 * np.abs(du_star).max()
+    assert st.win.value == n - 2
+
+
+def test_map_waits_for_s_min_column_pairs(oracle_lib):
+    st, free, _, _ = _window_case(oracle_lib, 7, 8, 8, 1)
+    st.P.s_min = 8
+    dab = oracle_lib.ab4(st.P.dt, *[c.copy() for c in st.vh])
+    rec, _, guess = st.step(want_guess=True)        # step 9: 7 column pairs
+    assert rec.s_eff == 0 and rec.pick == -1
+    np.testing.assert_array_equal(guess, np.where(free, dab, 0.0))
+    dab = oracle_lib.ab4(st.P.dt, *[c.copy() for c in st.vh])
+    rec, _, guess = st.step(want_guess=True)        # step 10: 8 column pairs
+    assert rec.s_eff == 8 and rec.first == 1
+    assert np.abs(guess - np.where(free, dab, 0.0)).max() > 0

@@ -60,8 +60,9 @@ extern "C" {
 /* Kinds of initial guess for the next step's increment. */
 #define EBE_PRED_ZERO 0      /* x-bar = 0 */
 #define EBE_PRED_AB4 1       /* Adams-Bashforth 4-step estimate (Sec. 3.2) */
-#define EBE_PRED_SNAPSHOT 2  /* AB4 + regional snapshot map (Sec. 3.2) */
-#define EBE_PRED_LEARNED 3   /* two candidates: the kind-2 guess and the AB4
+#define EBE_PRED_SNAPSHOT 2  /* AB4 + regional snapshot map (Sec. 3.2) over
+                                a guarded window (see ebe_predict) */
+#define EBE_PRED_LEARNED 3   /* the kind-2 guess judged against the AB4
                                 increment plus a node-wise network estimate of
                                 its error (see "Learned predictor" below); the
                                 one with the smaller initial residual is kept
@@ -107,7 +108,15 @@ typedef struct {
     int32_t precision;      /* EBE_PREC_*: how Algorithm 1 is run (see below) */
     int32_t inner_iters;    /* mixed precision: inner PCG trips per outer trip at most
                                (<= 0: 16) */
-    int32_t reserved[4];
+    int32_t s_min;          /* snapshot map used only once its window holds at least
+                               min(s_min, s) column pairs (<= 0: 8, the lower end of the
+                               paper's range 8 <= s <= 32, Sec. 4 / Fig. 3); AB4 alone before */
+    int32_t fixed_window;   /* 0 (default): guarded window -- whenever the map is used, the
+                               AB4 guess is evaluated too and kept when its initial residual
+                               is strictly smaller, and the window then restarts at that step
+                               (see "Snapshot window" below); 1: the map's guess is always
+                               used and the window never restarts */
+    int32_t reserved[2];
 } ebe_config;
 
 typedef struct {
@@ -123,7 +132,7 @@ typedef struct {
 
 typedef struct {
     int32_t it;         /* index of the step just completed (1-based) */
-    int32_t s_eff;      /* snapshot columns used, min(s, it - 2), 0 if none */
+    int32_t s_eff;      /* snapshot column pairs used by the map (0: map not used) */
     int32_t iters;
     int32_t restarts;
     int32_t status;
@@ -131,10 +140,25 @@ typedef struct {
     double res0, res_rec, res_true, bnorm;
     int32_t learned;        /* kind 3: 1 the learned candidate was kept, 0 the snapshot
                                prediction; -1 if no candidate was evaluated this step */
-    int32_t reserved;
+    int32_t first;          /* the window held the AB errors e^first .. e^{it-1} (0: no map) */
     double res0_snapshot;   /* kind 3: ||b - A x||/||b|| of both candidates (free rows) */
     double res0_learned;
+    int32_t map_kept;       /* guarded window: 1 the map's guess was kept, 0 the AB4 guess
+                               (the window restarted at this step); -1 no comparison */
+    int32_t reserved;
+    double res0_map;        /* guarded window: ||b - A x||/||b|| of the map's and of the */
+    double res0_ab;         /* AB4 guess (free rows; 0 without a comparison) */
 } ebe_step_stats;
+
+typedef struct {
+    int32_t s_eff;          /* as in ebe_step_stats, for the step ebe_predict looks at */
+    int32_t first;
+    int32_t map_kept;       /* 1 map's guess returned, 0 AB4's, -1 no comparison */
+    int32_t learned;        /* kind 3: 1 learned candidate returned, 0 not, -1 not evaluated */
+    double res0;            /* ||b - A x-bar|| / ||b|| of the returned guess (free rows) */
+    double res0_map, res0_ab, res0_learned;   /* candidates compared (else 0) */
+    double bnorm;           /* ||b|| of the step's right-hand side */
+} ebe_pred_stats;
 
 /* Version string of the library. */
 const char* ebe_version(void);
@@ -197,10 +221,24 @@ int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* 
 
 /* Initial guess of the next step's increment from the stored history
  * (Eq. predictor with the concrete predictor of Sec. 3.2 chosen by
- * cfg.predictor).  f_next is accepted for interface completeness and unused
- * by the built-in predictors.  *s_eff receives the snapshot columns used
- * (may be NULL).  The state is not modified. */
-int ebe_predict(ebe_handle* h, const double* f_next, double* dxbar, int32_t* s_eff);
+ * cfg.predictor): exactly the guess ebe_step would start from with the same
+ * f_ext (f_next, device, may be NULL) and base_acc (host [3], may be NULL),
+ * whose right-hand side the guarded window and kind 3 need to compare
+ * candidates.  dxbar: device [3N] out.  stats (may be NULL): window, picks and
+ * initial residuals (filling it synchronises the stream).  The state is not
+ * modified: a window restart implied by the comparison happens only in
+ * ebe_step.
+ *
+ * Snapshot window (kinds 2 and 3).  Step n fits the regional map on the AB
+ * errors e^first .. e^{n-1}, first = max(w, n - 1 - s): inputs e^first ..
+ * e^{n-2}, outputs e^{first+1} .. e^{n-1}, query e^{n-1}, s_eff = n - 1 - first
+ * column pairs; w = 1 at rest.  The map is used once s_eff >= min(s_min, s).
+ * Unless cfg.fixed_window, the AB4 guess is then evaluated too (one more
+ * matvec) and kept when ||b - A x|| is strictly smaller; ebe_step then sets
+ * w = n, discarding the columns that span the change of regime (the start
+ * from rest, a kink of the input) that made the map lose. */
+int ebe_predict(ebe_handle* h, const double* f_next, const double* base_acc, double* dxbar,
+                ebe_pred_stats* stats);
 
 /* Algorithm 1 (or its mixed-precision form, cfg.precision): solve A_bc x = b to
  * ||b - A x|| / ||b|| < tol starting from the guess in x (overwritten with the
@@ -220,11 +258,12 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
 /* Checkpoint / resume.  u, v, a: device [3N] each, caller order.
  * History: vhist device [4][3N] = v^it, v^(it-1), v^(it-2), v^(it-3);
  * ring device [s+1][3N] with e^j = du^j - du_AB^j in slot (j-1) mod (s+1);
- * it = completed steps. */
+ * it = completed steps; win_start = w, the first step whose AB error may
+ * enter the snapshot window (>= 1). */
 int ebe_get_state(ebe_handle* h, double* u, double* v, double* a);
 int ebe_set_state(ebe_handle* h, const double* u, const double* v, const double* a);
-int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it);
-int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it);
+int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it, int32_t* win_start);
+int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it, int32_t win_start);
 
 /* Block until all work enqueued on the handle's stream is done. */
 int ebe_sync(ebe_handle* h);
@@ -284,8 +323,8 @@ int ebe_mlp_set(ebe_handle* h, const float* params, const float* scales);
 int ebe_mlp_get(ebe_handle* h, float* params, float* scales);
 /* Inference kernel on given inputs: x device [n][15] (already scaled), y
  * device [n][3] (network outputs, unscaled).  With predictor kind 3,
- * ebe_predict returns the learned candidate (f_next: the force of the new
- * step, device [3N], or NULL for zero). */
+ * ebe_predict returns the guess ebe_step would keep (the learned candidate
+ * when its initial residual is the smaller). */
 int ebe_mlp_forward(ebe_handle* h, int64_t n, const float* x, float* y);
 /* Loss and gradient over n (1..8192) samples: x device [n][15], t device
  * [n][3] (scaled targets); grad device [5379] out; loss host out or NULL. */
@@ -316,7 +355,8 @@ int ebe_mlp_train(ebe_handle* h, int32_t steps, int32_t batch, const int64_t* id
  * case: own alpha, beta, stop test and iteration count, stopped cases masked
  * out of the shared element passes).  Every case follows the single-case
  * step of ebe_step (right-hand side, AB4 + regional snapshot map, refine to
- * tol, Newmark).  Each mesh added forms a group of n_cases cases; the group's
+ * tol, Newmark; every case has its own guarded snapshot window, see
+ * ebe_predict).  Each mesh added forms a group of n_cases cases; the group's
  * element pass works on tiles of case_tile cases (1, 2, 4 or 8) with element
  * patches of 256 / case_tile elements and `chunks` persistent workgroups per
  * tile, chosen by timing every candidate when ebe_batch_assemble is asked to
@@ -331,10 +371,12 @@ typedef struct {
     int32_t iters;      /* PCG trips of this case in the last step */
     int32_t restarts;
     int32_t status;     /* EBE_OK or EBE_NOT_CONVERGED */
-    int32_t s_eff;
+    int32_t s_eff;      /* snapshot column pairs of this case's map (0: not used) */
     double res0;        /* relative residual of the initial guess */
     double res_true;    /* relative true residual at exit */
     double bnorm;
+    int32_t first;      /* this case's window held e^first .. e^{it-1} (0: no map) */
+    int32_t map_kept;   /* guarded window: 1 map's guess kept, 0 AB4's (window restarted), -1 none */
 } ebe_batch_stats;
 
 int ebe_batch_create(const ebe_config* cfg, void* hip_stream, ebe_batch** out);

@@ -65,6 +65,7 @@ struct ebe_handle {
     int head = 0;  // vh[(head + j) & 3] = v^(it - j)
     double* ring = nullptr;
     int32_t it = 0;
+    int32_t win = 1;   // first step whose AB error may enter the snapshot window
     // scratch
     double *dab = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr};
     double *t0 = nullptr, *t1 = nullptr, *coef = nullptr, *gh = nullptr;
@@ -91,7 +92,7 @@ struct ebe_handle {
     double* msum = nullptr;          // [N] row sums of M
     double* x_alt = nullptr;         // [3N] learned candidate
     double* cand_part = nullptr;     // [2][res_grid] candidate residual partials
-    double* qbuf_alt = nullptr;      // matvec slots of the learned candidate
+    double* qbuf_alt = nullptr;      // matvec slots of the alternative guess (AB4 or learned)
     bool q_ready = false;            // qbuf already holds A x for the next solve's guess
     uint16_t* mlp_w = nullptr;       // BF16 weights
     float *mlp_wm = nullptr, *mlp_m = nullptr, *mlp_v = nullptr;
@@ -453,26 +454,31 @@ int run_solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
     return h->cfg.precision == EBE_PREC_FP64 ? solve(h, b, x, st) : solve_mixed(h, b, x, st);
 }
 
-int snapshot_columns(const ebe_handle* h, int n) {
+// Snapshot window of step n: AB errors e^first .. e^{n-1}, first = max(win,
+// n - 1 - s); returns the column pairs s_eff = n - 1 - first when the map is
+// used (s_eff >= s_min), else 0.
+int snapshot_window(const ebe_handle* h, int n, int* first_out) {
+    *first_out = 0;
     if ((h->cfg.predictor != EBE_PRED_SNAPSHOT && h->cfg.predictor != EBE_PRED_LEARNED) || h->cfg.s < 1) return 0;
-    int s_eff = std::min(h->cfg.s, n - 2);
-    return s_eff >= 1 ? s_eff : 0;
+    const int first = std::max(h->win, n - 1 - h->cfg.s);
+    const int s_eff = n - 1 - first;
+    if (s_eff < std::max(1, std::min(h->cfg.s_min, h->cfg.s))) return 0;
+    *first_out = first;
+    return s_eff;
 }
 
-// Initial guess of step n = it + 1 into x; dab receives the AB4 increment.
-int predict_into(ebe_handle* h, double* x) {
+// AB4 increment into dab and the guess of step n = it + 1 into x: dab (or 0
+// for kind 0), plus the regional map over the window when it is used.
+int predict_into(ebe_handle* h, double* x, int* first) {
     hipStream_t s = h->stream;
     const int n = h->it + 1;
     launch_ab4(s, h->n3(), h->cfg.dt, h->vslot(0), h->vslot(1), h->vslot(2), h->vslot(3),
                h->cfg.predictor == EBE_PRED_ZERO ? 0 : 1, h->dab, x);
-    int s_eff = snapshot_columns(h, n);
+    int s_eff = snapshot_window(h, n, first);
     if (s_eff >= 1) {
         ColPtrs W{};
         const int S1 = h->cfg.s + 1;
-        for (int j = 0; j <= s_eff; ++j) {
-            int m = n - s_eff - 1 + j;  // e^m, stored in slot (m - 1) mod (s + 1)
-            W.c[j] = h->ring_slot((m - 1) % S1);
-        }
+        for (int j = 0; j <= s_eff; ++j) W.c[j] = h->ring_slot((*first + j - 1) % S1);   // e^{first + j}
         launch_gram_solve(s, W, s_eff, h->chunks, h->cfg.drop_tol, h->gh, h->coef);
         launch_pred_apply(s, W, s_eff, h->chunks, h->coef, h->dab, x);
     }
@@ -512,8 +518,6 @@ bool learned_due(const ebe_handle* h, int n) {
 
 void need_x_alt(ebe_handle* h) {
     if (!h->x_alt) h->x_alt = h->alloc<double>(h->n3());
-    if (!h->cand_part) h->cand_part = h->alloc<double>(2 * (size_t)res_grid(h->T.n_nodes));
-    if (!h->qbuf_alt) h->qbuf_alt = h->alloc<double>(3 * h->T.patch_nodes.size());
 }
 
 // After this many consecutive steps in which the kind-2 guess was kept, the
@@ -522,25 +526,60 @@ void need_x_alt(ebe_handle* h) {
 constexpr int kCandPatience = 8;
 constexpr int kCandProbe = 16;
 
-// Learned candidate = Adams-Bashforth increment (dab) + network estimate of
-// its error; keep whichever of it and the snapshot prediction (in x) has the
-// smaller initial residual ||b - A x||, in x.
-void choose_learned(ebe_handle* h, const double* f_int, const double* g) {
+// Keeps in x whichever of x (primary; its matvec slots already in qbuf when
+// q_ready) and x_alt has the smaller initial residual ||b - A x|| over the free
+// rows, with that guess's matvec slots in qbuf (ties keep the primary).
+void choose(ebe_handle* h, const double* x_alt, int which) {
     hipStream_t s = h->stream;
+    const int gr = res_grid(h->T.n_nodes);
+    if (!h->q_ready) launch_ebe_apply(s, h->dp, h->x, true, h->cM, h->cK, h->qbuf);
+    launch_cand_res(s, h->dn, h->qbuf, h->b, h->cand_part);
+    launch_ebe_apply(s, h->dp, x_alt, true, h->cM, h->cK, h->qbuf_alt);
+    launch_cand_res(s, h->dn, h->qbuf_alt, h->b, h->cand_part + gr);
+    launch_cand_select(s, h->dn, h->cand_part, h->cand_part + gr, h->x, x_alt, h->qbuf, h->qbuf_alt,
+                       (int64_t)(3 * h->T.patch_nodes.size()), h->sc, which);
+    check_launch();
+    h->q_ready = true;   // qbuf holds the kept guess's matvec: the solve skips its first one
+}
+
+// Learned candidate = Adams-Bashforth increment (dab) + network estimate of
+// its error, judged against the guess in x.
+void choose_learned(ebe_handle* h, const double* f_int, const double* g) {
     need_x_alt(h);
     MlpState S = mlp_state(h, f_int, g);
     S.xs = h->dab;
     S.xl = h->x_alt;
-    launch_mlp_infer_state(s, h->mlp_w, S, h->T.n_nodes);
-    const int gr = res_grid(h->T.n_nodes);
-    launch_ebe_apply(s, h->dp, h->x, true, h->cM, h->cK, h->qbuf);
-    launch_cand_res(s, h->dn, h->qbuf, h->b, h->cand_part);
-    launch_ebe_apply(s, h->dp, h->x_alt, true, h->cM, h->cK, h->qbuf_alt);
-    launch_cand_res(s, h->dn, h->qbuf_alt, h->b, h->cand_part + gr);
-    launch_cand_select(s, h->dn, h->cand_part, h->cand_part + gr, h->x, h->x_alt, h->qbuf, h->qbuf_alt,
-                       (int64_t)(3 * h->T.patch_nodes.size()), h->sc);
-    check_launch();
-    h->q_ready = true;   // qbuf holds the kept guess's matvec: the solve skips its first one
+    launch_mlp_infer_state(h->stream, h->mlp_w, S, h->T.n_nodes);
+    choose(h, h->x_alt, 0);
+}
+
+// What the guess of the next step was made of (host-side facts; the picks are
+// device scalars read back with the solve's).
+struct GuessInfo {
+    int n = 0, s_eff = 0, first = 0;
+    bool guarded = false;   // map's guess compared with the AB4 guess
+    bool learned = false;   // learned candidate evaluated
+};
+
+// Right-hand side of step n = it + 1 into b and its guess into x (Eq.
+// predictor with the predictor of Sec. 3.2): AB4; the regional map once the
+// window holds s_min column pairs; unless the window is fixed, the AB4 guess
+// evaluated too and kept when its residual is strictly smaller (the caller
+// then restarts the window); kind 3: the learned candidate against the result.
+// The state is not modified.
+GuessInfo guess_into(ebe_handle* h, const double* f_int, const double* g) {
+    GuessInfo info;
+    info.n = h->it + 1;
+    rhs_into(h, f_int, g, h->b);
+    h->q_ready = false;
+    info.s_eff = predict_into(h, h->x, &info.first);
+    if (info.s_eff > 0 && !h->cfg.fixed_window) {
+        choose(h, h->dab, 1);
+        info.guarded = true;
+    }
+    info.learned = learned_due(h, info.n) && (h->cand_losses < kCandPatience || info.n % kCandProbe == 0);
+    if (info.learned) choose_learned(h, f_int, g);
+    return info;
 }
 
 void need_mlp(ebe_handle* h) {
@@ -625,6 +664,7 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     if (c.patch_elems <= 0) c.patch_elems = kMaxPatchElems;
     if (c.inner_iters <= 0) c.inner_iters = 16;
     if (c.inner_tol <= 0) c.inner_tol = 1e-2;
+    if (c.s_min <= 0) c.s_min = 8;
     ebe_handle* h = new (std::nothrow) ebe_handle();
     if (!h) {
         g_create_error = "out of memory";
@@ -716,6 +756,8 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->gh = h->alloc<double>((size_t)kGhStride * T.chunk_region.size());
         h->sc = h->alloc<DevScalars>(1);
         h->pap_part = h->alloc<double>(pcg_ebe_grid(h->dp));
+        h->cand_part = h->alloc<double>(2 * (size_t)res_grid(N));
+        h->qbuf_alt = h->alloc<double>(3 * PN);
         h->res_part = h->alloc<double>(2 * kResArrays * (size_t)res_grid(N));
         if (h->cfg.precision != EBE_PREC_FP64) {
             h->r_in = h->alloc<float>(n3);
@@ -757,6 +799,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         HIPCHK(hipStreamSynchronize(s));
         h->head = 0;
         h->it = 0;
+        h->win = 1;
         h->par = 0;
         h->last_iters = 0;
         h->assembled = true;
@@ -830,28 +873,46 @@ int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* 
     });
 }
 
-int ebe_predict(ebe_handle* h, const double* f_next, double* dxbar, int32_t* s_eff) {
+int ebe_predict(ebe_handle* h, const double* f_next, const double* base_acc, double* dxbar, ebe_pred_stats* stats) {
     return guarded(h, [&]() -> int {
         need_assembled(h);
         need_ptr(dxbar, "dxbar");
-        int se = predict_into(h, h->t1);
-        if (learned_due(h, h->it + 1)) {
-            const double* f_int = nullptr;
-            if (f_next) {
-                to_internal(h, f_next, h->t0);
-                f_int = h->t0;
-            }
-            need_x_alt(h);
-            MlpState S = mlp_state(h, f_int, nullptr);
-            S.xs = h->dab;
-            S.xl = h->x_alt;
-            launch_mlp_infer_state(h->stream, h->mlp_w, S, h->T.n_nodes);
-            to_user(h, h->x_alt, dxbar);
-        } else {
-            to_user(h, h->t1, dxbar);
+        hipStream_t s = h->stream;
+        const double* f_int = nullptr;
+        if (f_next) {
+            to_internal(h, f_next, h->t0);
+            f_int = h->t0;
         }
+        GuessInfo info = guess_into(h, f_int, base_acc);
+        to_user(h, h->x, dxbar);
+        if (stats) {
+            const int gr = res_grid(h->T.n_nodes);
+            if (!h->q_ready) launch_ebe_apply(s, h->dp, h->x, true, h->cM, h->cK, h->qbuf);
+            launch_cand_res(s, h->dn, h->qbuf, h->b, h->cand_part);
+            launch_sum_partials(s, h->cand_part, gr, &h->sc->guess_rr);
+            launch_cand_res(s, h->dn, nullptr, h->b, h->cand_part);
+            launch_sum_partials(s, h->cand_part, gr, &h->sc->guess_bb);
+            check_launch();
+            HIPCHK(hipMemcpyAsync(h->sc_host, h->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+            sync_stream(h);
+            const DevScalars& S = *h->sc_host;
+            const double bn = std::sqrt(S.guess_bb);
+            auto rel = [&](double rr) { return bn > 0 ? std::sqrt(rr) / bn : std::sqrt(rr); };
+            *stats = ebe_pred_stats{};
+            stats->s_eff = info.s_eff;
+            stats->first = info.first;
+            stats->map_kept = info.guarded ? 1 - S.guard_pick : -1;
+            stats->learned = info.learned ? S.cand_pick : -1;
+            stats->res0 = rel(S.guess_rr);
+            stats->bnorm = bn;
+            if (info.guarded) {
+                stats->res0_map = rel(S.guard_rr[0]);
+                stats->res0_ab = rel(S.guard_rr[1]);
+            }
+            if (info.learned) stats->res0_learned = rel(S.cand_rr[1]);
+        }
+        h->q_ready = false;
         check_launch();
-        if (s_eff) *s_eff = se;
         return EBE_OK;
     });
 }
@@ -880,13 +941,10 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
             to_internal(h, f_ext, h->t0);
             f_int = h->t0;
         }
-        rhs_into(h, f_int, base_acc, h->b);
-        const int n = h->it + 1;
-        int s_eff = predict_into(h, h->x);
+        GuessInfo info = guess_into(h, f_int, base_acc);
+        const int n = info.n;
         const bool collect = h->coll_k > 0 && n >= kLearnFirstStep && h->samples_n + h->coll_k <= h->samples_cap;
         if (collect) launch_collect_pre(s, h->coll_nodes, h->coll_k, h->dab, h->coll_stage);
-        const bool learned = learned_due(h, n) && (h->cand_losses < kCandPatience || n % kCandProbe == 0);
-        if (learned) choose_learned(h, f_int, base_acc);
         double* slot = h->cfg.s >= 1 ? h->ring_slot((n - 1) % (h->cfg.s + 1)) : nullptr;
         ebe_solve_stats st{};
         // without sample collection (which reads the state before the update) the
@@ -902,22 +960,27 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
         }
         h->post_newmark = false;
         if (rc < 0) return rc;
-        if (learned) h->cand_losses = h->sc_host->cand_pick ? 0 : h->cand_losses + 1;
+        const DevScalars& S = *h->sc_host;
+        if (info.learned) h->cand_losses = S.cand_pick ? 0 : h->cand_losses + 1;
+        // the AB4 guess beat the map: its window spans a change of regime and restarts here
+        if (info.guarded && S.guard_pick) h->win = n;
         if (collect) {
-            MlpState S = mlp_state(h, f_int, base_acc);
-            launch_collect_post(s, S, h->coll_nodes, h->coll_k, h->x, h->coll_stage,
+            MlpState MS = mlp_state(h, f_int, base_acc);
+            launch_collect_post(s, MS, h->coll_nodes, h->coll_k, h->x, h->coll_stage,
                                 h->samples + h->samples_n * kMlpSample);
             h->samples_n += h->coll_k;
         }
-        const int done = h->sc_host->done;
+        const int done = S.done;
         const bool updated = !collect && (done == DONE_CONVERGED || done == DONE_MAXITER);
         if (!updated) launch_newmark(s, h->n3(), h->cfg.dt, h->x, h->dab, h->u, h->vslot(0), h->vslot(3), h->a, slot);
         check_launch();
         h->head = (h->head + 3) & 3;
         h->it = n;
         if (stats) {
+            *stats = ebe_step_stats{};
             stats->it = n;
-            stats->s_eff = s_eff;
+            stats->s_eff = info.s_eff;
+            stats->first = info.first;
             stats->iters = st.iters;
             stats->restarts = st.restarts;
             stats->inner_iters = st.inner_iters;
@@ -926,15 +989,16 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
             stats->res_rec = st.res_rec;
             stats->res_true = st.res_true;
             stats->bnorm = st.bnorm;
-            stats->learned = -1;
-            stats->res0_snapshot = stats->res0_learned = 0.0;
-            if (learned) {
-                const DevScalars& S = *h->sc_host;
-                stats->learned = S.cand_pick;
-                if (st.bnorm > 0) {
-                    stats->res0_snapshot = std::sqrt(S.cand_rr[0]) / st.bnorm;
-                    stats->res0_learned = std::sqrt(S.cand_rr[1]) / st.bnorm;
-                }
+            auto rel = [&](double rr) { return st.bnorm > 0 ? std::sqrt(rr) / st.bnorm : 0.0; };
+            stats->map_kept = info.guarded ? 1 - S.guard_pick : -1;
+            if (info.guarded) {
+                stats->res0_map = rel(S.guard_rr[0]);
+                stats->res0_ab = rel(S.guard_rr[1]);
+            }
+            stats->learned = info.learned ? S.cand_pick : -1;
+            if (info.learned) {
+                stats->res0_snapshot = rel(S.cand_rr[0]);
+                stats->res0_learned = rel(S.cand_rr[1]);
             }
         }
         return rc;
@@ -963,7 +1027,7 @@ int ebe_set_state(ebe_handle* h, const double* u, const double* v, const double*
     });
 }
 
-int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it) {
+int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it, int32_t* win_start) {
     return guarded(h, [&]() -> int {
         need_assembled(h);
         const int64_t n3 = h->n3();
@@ -972,21 +1036,24 @@ int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it) {
         if (ring)
             for (int k = 0; k <= h->cfg.s; ++k) to_user(h, h->ring_slot(k), ring + k * n3);
         if (it) *it = h->it;
+        if (win_start) *win_start = h->win;
         check_launch();
         return EBE_OK;
     });
 }
 
-int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it) {
+int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it, int32_t win_start) {
     return guarded(h, [&]() -> int {
         need_assembled(h);
         if (it < 0) throw Arg{"it must be non-negative"};
+        if (win_start < 1) throw Arg{"win_start must be at least 1"};
         const int64_t n3 = h->n3();
         if (vhist)
             for (int j = 0; j < 4; ++j) to_internal(h, vhist + j * n3, h->vslot(j));
         if (ring)
             for (int k = 0; k <= h->cfg.s; ++k) to_internal(h, ring + k * n3, h->ring_slot(k));
         h->it = it;
+        h->win = win_start;
         check_launch();
         return EBE_OK;
     });
@@ -1050,6 +1117,7 @@ int ebe_reset(ebe_handle* h) {
         check_launch();
         h->head = 0;
         h->it = 0;
+        h->win = 1;
         h->last_iters = 0;
         h->cand_losses = 0;
         return EBE_OK;

@@ -546,6 +546,51 @@ __global__ void k_bzero_rhs_cases(const DevScalars* sc, int64_t n3, double* x) {
         x[(int64_t)c * n3 + i] = 0.0;
 }
 
+// Guarded snapshot window, per case: free-row ||b - A x||^2 partials of one
+// guess (its slots in A.qbuf) into part[c][g_upd].
+__global__ __launch_bounds__(256) void k_bcand_res(BNodeArgs A, double* part) {
+    const int c = blockIdx.y;
+    const int64_t off = (int64_t)c * 3 * A.N.n;
+    const double* q = A.qbuf + 3 * (int64_t)c * A.pn;
+    int64_t lo, hi;
+    node_range(A.N.n, blockIdx.x, gridDim.x, lo, hi);
+    double v = 0.0;
+    for (int64_t n = lo + threadIdx.x; n < hi; n += blockDim.x) {
+        double q0, q1, q2;
+        gather_slots(A.N, q, n, q0, q1, q2);
+        const uint8_t fm = A.N.fixmask[n];
+        const int64_t i = off + 3 * n;
+        const double r0 = (fm & 1) ? 0.0 : A.b[i] - q0;
+        const double r1 = (fm & 2) ? 0.0 : A.b[i + 1] - q1;
+        const double r2 = (fm & 4) ? 0.0 : A.b[i + 2] - q2;
+        v += r0 * r0 + r1 * r1 + r2 * r2;
+    }
+    v = block_bcast_sum(v);
+    if (threadIdx.x == 0) part[(int64_t)c * gridDim.x + blockIdx.x] = v;
+}
+
+// Per case: the map's guess (in x, partials part_m) against the AB4 guess
+// (dab, partials part_a); the AB4 guess replaces x when its residual is
+// strictly smaller.  Every workgroup of a case sums the partials in the same
+// order; workgroup 0 records the result in the case's scalars.
+__global__ __launch_bounds__(256) void k_bguard_select(BNodeArgs A, const double* part_m, const double* part_a,
+                                                       const double* dab) {
+    const int c = blockIdx.y;
+    const double rm = block_bcast_sum(threadIdx.x < A.g_upd ? part_m[(int64_t)c * A.g_upd + threadIdx.x] : 0.0);
+    const double ra = block_bcast_sum(threadIdx.x < A.g_upd ? part_a[(int64_t)c * A.g_upd + threadIdx.x] : 0.0);
+    const bool pick = ra < rm;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.sc[c].guard_rr[0] = rm;
+        A.sc[c].guard_rr[1] = ra;
+        A.sc[c].guard_pick = pick ? 1 : 0;
+    }
+    if (!pick) return;
+    const int64_t off = (int64_t)c * 3 * A.N.n;
+    int64_t lo, hi;
+    node_range(A.N.n, blockIdx.x, gridDim.x, lo, hi);
+    for (int64_t i = 3 * lo + threadIdx.x; i < 3 * hi; i += blockDim.x) A.x[off + i] = dab[off + i];
+}
+
 __global__ void k_set_trip(int* trip, int v) { *trip = v; }
 __global__ void k_trip_inc(int* trip) { *trip += 1; }
 
@@ -618,6 +663,15 @@ void launch_bcombine(hipStream_t s, const BNodeArgs& A, const double* p, const d
 
 void launch_bzero_rhs_cases(hipStream_t s, const DevScalars* sc, int r, int64_t n3, double* x) {
     hipLaunchKernelGGL(k_bzero_rhs_cases, dim3(64, r), dim3(256), 0, s, sc, n3, x);
+}
+
+void launch_bcand_res(hipStream_t s, const BNodeArgs& A, double* part) {
+    hipLaunchKernelGGL(k_bcand_res, dim3(A.g_upd, A.r), dim3(256), 0, s, A, part);
+}
+
+void launch_bguard_select(hipStream_t s, const BNodeArgs& A, const double* part_m, const double* part_a,
+                          const double* dab) {
+    hipLaunchKernelGGL(k_bguard_select, dim3(A.g_upd, A.r), dim3(256), 0, s, A, part_m, part_a, dab);
 }
 
 void launch_set_trip(hipStream_t s, int* trip, int v) { hipLaunchKernelGGL(k_set_trip, dim3(1), dim3(1), 0, s, trip, v); }

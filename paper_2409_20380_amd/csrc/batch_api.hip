@@ -90,6 +90,7 @@ struct Group {
     double* binv6 = nullptr;
     double* part = nullptr;  // update partials [2][kResArrays][r][g_upd]
     double* pap = nullptr;   // (p, A p) partials [r][chunks]
+    double* cand = nullptr;  // guarded window: residual partials of the two guesses [2][r][g_upd]
 };
 
 }  // namespace
@@ -115,6 +116,9 @@ struct ebe_batch {
     int* trip = nullptr;
     DevChunks chunks{};
     int head = 0, it = 0, par = 0, last_iters = 0;
+    std::vector<int> win;          // per case: first step whose AB error may enter its snapshot window
+    int32_t* lo_dev = nullptr;     // per case: first window column its regions use
+    int32_t* lo_host = nullptr;    // pinned staging of lo_dev
     bool use_graph = true;
     int graph_trips = 8;
     hipGraph_t graph = nullptr;
@@ -454,6 +458,7 @@ int ebe_batch_create(const ebe_config* cfg, void* stream, ebe_batch** out) {
     if (c.max_iter <= 0) c.max_iter = 10000;
     if (c.drop_tol <= 0) c.drop_tol = 1e-6;
     if (c.region_nodes <= 0) c.region_nodes = 512;
+    if (c.s_min <= 0) c.s_min = 8;
     if (!(c.dt > 0) || !(c.tol > 0) || c.s < 0 || c.s > kMaxCols - 1 || c.predictor < 0 || c.predictor > 2 ||
         c.rayleigh_alpha < 0 || c.rayleigh_beta < 0 || c.precision != EBE_PREC_FP64) {
         g_batch_create_error = "invalid configuration (need dt > 0, tol > 0, 0 <= s <= 32, predictor 0..2, FP64)";
@@ -480,6 +485,7 @@ int ebe_batch_destroy(ebe_batch* b) {
     b->release();
     if (b->sc_host) (void)hipHostFree(b->sc_host);
     if (b->g_host) (void)hipHostFree(b->g_host);
+    if (b->lo_host) (void)hipHostFree(b->lo_host);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return EBE_OK;
@@ -576,19 +582,27 @@ int ebe_batch_assemble(ebe_batch* b, int32_t tune) {
         b->g_dev = M.alloc<double>(3 * (size_t)b->C);
         if (b->sc_host) (void)hipHostFree(b->sc_host);
         if (b->g_host) (void)hipHostFree(b->g_host);
+        if (b->lo_host) (void)hipHostFree(b->lo_host);
         b->sc_host = nullptr;
         b->g_host = nullptr;
+        b->lo_host = nullptr;
         BCHK(hipHostMalloc((void**)&b->sc_host, b->C * sizeof(DevScalars), hipHostMallocDefault));
         BCHK(hipHostMalloc((void**)&b->g_host, 3 * b->C * sizeof(double), hipHostMallocDefault));
+        BCHK(hipHostMalloc((void**)&b->lo_host, b->C * sizeof(int32_t), hipHostMallocDefault));
+        b->lo_dev = M.alloc<int32_t>(b->C);
+        b->win.assign(b->C, 1);
         BCHK(hipMemsetAsync(b->sc, 0, b->C * sizeof(DevScalars), s));
         // regions of every case of every group, in stacked node order, cut into
         // node chunks (the host vectors live until the stream is synchronised below)
         if (nodes > INT32_MAX) throw BErr{EBE_E_INVALID_ARG, "batch too large"};
-        std::vector<int32_t> rs, cs, cr, rc;
+        std::vector<int32_t> rs, cs, cr, rc, rcase;
         for (auto& g : b->groups) {
             const int64_t base = g.dof_off / 3;
             for (int c = 0; c < g.r; ++c)
-                for (int k = 0; k < g.T.n_regions; ++k) rs.push_back((int32_t)(base + c * g.N + g.T.region_start[k]));
+                for (int k = 0; k < g.T.n_regions; ++k) {
+                    rs.push_back((int32_t)(base + c * g.N + g.T.region_start[k]));
+                    rcase.push_back(g.case0 + c);
+                }
         }
         rs.push_back((int32_t)nodes);
         region_chunks(rs, cs, cr, rc);
@@ -600,9 +614,12 @@ int ebe_batch_assemble(ebe_batch* b, int32_t tune) {
         BCHK(hipMemcpyAsync(d_cs, cs.data(), cs.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         BCHK(hipMemcpyAsync(d_cr, cr.data(), cr.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         BCHK(hipMemcpyAsync(d_rc, rc.data(), rc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        int32_t* d_rcase = M.alloc<int32_t>(rcase.size());
+        BCHK(hipMemcpyAsync(d_rcase, rcase.data(), rcase.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
         b->chunks.start = d_cs;
         b->chunks.region = d_cr;
         b->chunks.first = d_rc;
+        b->chunks.region_case = d_rcase;
         b->coef = M.alloc<double>(32 * (size_t)b->chunks.n_regions);
         b->gh = M.alloc<double>((size_t)kGhStride * b->chunks.n_chunks);
         // per group: block-Jacobi inverse (shared by its cases) and partials
@@ -613,6 +630,7 @@ int ebe_batch_assemble(ebe_batch* b, int32_t tune) {
             launch_diag_finalize(s, g.dn, q6, g.binv6);
             g.part = M.alloc<double>(2 * (size_t)kResArrays * g.r * g.g_upd);
             g.pap = M.alloc<double>((size_t)g.r * g.chunks);
+            g.cand = M.alloc<double>(2 * (size_t)g.r * g.g_upd);
         }
         for (double* v : {b->u, b->a, b->vh[0], b->vh[1], b->vh[2], b->vh[3], b->p[0], b->p[1], b->x})
             launch_zero(s, dof, v);
@@ -660,6 +678,7 @@ int ebe_batch_reset(ebe_batch* b) {
         check_launch();
         b->head = b->it = 0;
         b->last_iters = 0;
+        b->win.assign(b->C, 1);
         return EBE_OK;
     });
 }
@@ -708,22 +727,55 @@ int ebe_batch_step(ebe_batch* b, const double* base_acc, ebe_batch_stats* stats)
             launch_bebe(s, MODE_RHS, A, g.ct, g.chunks);
             launch_bcombine(s, node_args(b, g), nullptr, nullptr, b->b + g.dof_off, 2);
         }
-        // Adams-Bashforth 4 and the regional snapshot map over the stacked vectors
+        // Adams-Bashforth 4 and the regional snapshot map over the stacked vectors; every
+        // case has its own window (see ebe_step), the regions of a case use the newest
+        // columns of the common window that its own window holds
         const int n = b->it + 1;
         launch_ab4(s, b->n3, c.dt, b->vslot(0), b->vslot(1), b->vslot(2), b->vslot(3),
                    c.predictor == EBE_PRED_ZERO ? 0 : 1, b->dab, b->x);
-        int s_eff = 0;
-        if (c.predictor == EBE_PRED_SNAPSHOT && c.s >= 1) s_eff = std::max(0, std::min(c.s, n - 2));
-        if (s_eff >= 1) {
+        std::vector<int> se(b->C, 0), first(b->C, 0);
+        int S = 0;
+        if (c.predictor == EBE_PRED_SNAPSHOT && c.s >= 1) {
+            const int s_min = std::max(1, std::min(c.s_min, c.s));
+            for (int k = 0; k < b->C; ++k) {
+                const int f = std::max(b->win[k], n - 1 - c.s);
+                if (n - 1 - f >= s_min) {
+                    se[k] = n - 1 - f;
+                    first[k] = f;
+                    S = std::max(S, se[k]);
+                }
+            }
+        }
+        const bool guarded = S >= 1 && !c.fixed_window;
+        if (S >= 1) {
             ColPtrs W{};
-            const int S1 = c.s + 1;
-            for (int jj = 0; jj <= s_eff; ++jj) W.c[jj] = b->ring_slot((n - s_eff - 1 + jj - 1) % S1);
-            launch_gram_solve(s, W, s_eff, b->chunks, c.drop_tol, b->gh, b->coef);
-            launch_pred_apply(s, W, s_eff, b->chunks, b->coef, b->dab, b->x);
+            const int S1 = c.s + 1, f0 = n - 1 - S;
+            for (int jj = 0; jj <= S; ++jj) W.c[jj] = b->ring_slot((f0 + jj - 1) % S1);   // e^{f0 + jj}
+            for (int k = 0; k < b->C; ++k) b->lo_host[k] = se[k] > 0 ? S - se[k] : S;
+            BCHK(hipMemcpyAsync(b->lo_dev, b->lo_host, b->C * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            launch_gram_solve(s, W, S, b->chunks, c.drop_tol, b->gh, b->coef, b->lo_dev);
+            launch_pred_apply(s, W, S, b->chunks, b->coef, b->dab, b->x);
+            if (guarded) {
+                for (auto& g : b->groups) {
+                    BNodeArgs N = node_args(b, g);
+                    BEbeArgs A = ebe_args(b, g);
+                    A.mask_in = 1;
+                    A.in0 = b->x + g.dof_off;
+                    launch_bebe(s, MODE_APPLY, A, g.ct, g.chunks);
+                    launch_bcand_res(s, N, g.cand);
+                    A.in0 = b->dab + g.dof_off;
+                    launch_bebe(s, MODE_APPLY, A, g.ct, g.chunks);
+                    launch_bcand_res(s, N, g.cand + (size_t)g.r * g.g_upd);
+                    launch_bguard_select(s, N, g.cand, g.cand + (size_t)g.r * g.g_upd, b->dab + g.dof_off);
+                }
+            }
         }
         check_launch();
         int rc = solve_batch(b);
         if (rc < 0) return rc;
+        // a case whose AB4 guess beat its map restarts its window at this step
+        for (int k = 0; k < b->C; ++k)
+            if (guarded && se[k] > 0 && b->sc_host[k].guard_pick) b->win[k] = n;
         double* slot = c.s >= 1 ? b->ring_slot((n - 1) % (c.s + 1)) : nullptr;
         launch_newmark(s, b->n3, c.dt, b->x, b->dab, b->u, b->vslot(0), b->vslot(3), b->a, slot);
         check_launch();
@@ -731,15 +783,18 @@ int ebe_batch_step(ebe_batch* b, const double* base_acc, ebe_batch_stats* stats)
         b->it = n;
         if (stats) {
             for (int k = 0; k < b->C; ++k) {
-                const DevScalars& S = b->sc_host[k];
+                const DevScalars& Sk = b->sc_host[k];
                 ebe_batch_stats& o = stats[k];
-                o.iters = S.iters;
-                o.restarts = S.restarts;
-                o.status = S.done == DONE_MAXITER ? EBE_NOT_CONVERGED : EBE_OK;
-                o.s_eff = s_eff;
-                o.res0 = S.res0;
-                o.res_true = S.bnorm > 0 ? S.res_true : 0.0;
-                o.bnorm = S.bnorm;
+                o = ebe_batch_stats{};
+                o.iters = Sk.iters;
+                o.restarts = Sk.restarts;
+                o.status = Sk.done == DONE_MAXITER ? EBE_NOT_CONVERGED : EBE_OK;
+                o.s_eff = se[k];
+                o.first = first[k];
+                o.map_kept = (guarded && se[k] > 0) ? 1 - Sk.guard_pick : -1;
+                o.res0 = Sk.res0;
+                o.res_true = Sk.bnorm > 0 ? Sk.res_true : 0.0;
+                o.bnorm = Sk.bnorm;
             }
         }
         return rc;

@@ -27,6 +27,14 @@ struct DevScalars {
     double cand_rr[2];
     int32_t cand_pick;
     int32_t pad_;
+    // snapshot-map guard: squared free-row residuals of the map's guess (0)
+    // and of the Adams-Bashforth guess (1); guard_pick = 1 when the latter was
+    // kept (strictly smaller); not reset by a solve
+    double guard_rr[2];
+    int32_t guard_pick;
+    int32_t pad2_;
+    double guess_rr;   // ||b - A x||^2 of the last guess evaluated by ebe_predict (free rows)
+    double guess_bb;   // ||b||^2 of the same right-hand side (free rows)
 };
 
 enum { DONE_RUNNING = 0, DONE_CONVERGED = 1, DONE_NONFINITE = 2, DONE_MAXITER = 3, DONE_ZERO_RHS = 4 };
@@ -159,10 +167,14 @@ struct DevChunks {
     const int32_t* start = nullptr;    // [n_chunks+1] internal node ranges
     const int32_t* region = nullptr;   // [n_chunks] region of each chunk
     const int32_t* first = nullptr;    // [n_regions+1] first chunk of each region
+    const int32_t* region_case = nullptr;  // batched ensembles: [n_regions] case of each region
 };
-// gh: [n_chunks][kGhStride] partial Grams; coef: [n_regions][32].
+// gh: [n_chunks][kGhStride] partial Grams; coef: [n_regions][32].  case_lo
+// (batched ensembles, may be NULL): region r uses only the columns j >=
+// case_lo[C.region_case[r]] of the window (its case's shorter window; the
+// older columns get zero coefficients).
 void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double drop, double* gh,
-                       double* coef);
+                       double* coef, const int32_t* case_lo = nullptr);
 void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, const double* coef,
                        const double* dab, double* x);
 // guard (may be NULL): run only once the solve's stop flag reads converged or max_iter
@@ -221,6 +233,11 @@ void launch_bcheck_finalize(hipStream_t s, const BNodeArgs& A, double tol);
 // mode 0: slot sums; 1: A_bc (fixed rows take p); 2: f + slot sums, fixed rows zero
 void launch_bcombine(hipStream_t s, const BNodeArgs& A, const double* p, const double* f, double* out, int mode);
 void launch_bzero_rhs_cases(hipStream_t s, const DevScalars* sc, int r, int64_t n3, double* x);
+// Guarded snapshot window per case: residual partials of a guess, part [r][g_upd]; then keep
+// dab in x for the cases whose AB4 residual is strictly smaller (recorded in the case scalars).
+void launch_bcand_res(hipStream_t s, const BNodeArgs& A, double* part);
+void launch_bguard_select(hipStream_t s, const BNodeArgs& A, const double* part_m, const double* part_a,
+                          const double* dab);
 void launch_set_trip(hipStream_t s, int* trip, int v);
 void launch_trip_inc(hipStream_t s, int* trip);
 
@@ -260,13 +277,17 @@ struct MlpTrain {
 };
 // Row sums of M (x component of M 1) per node, from an unmasked M-only matvec.
 void launch_msum(hipStream_t s, const DevNodes& N, const double* qbuf, double* msum);
-// Candidate selection of the learned predictor: free-row ||b - A x||^2
-// partials of a candidate (slot sums in qbuf), then keep the candidate with
+// Choice between two guesses: free-row ||b - A x||^2 partials of a candidate
+// (slot sums in qbuf; qbuf NULL gives ||b||^2), then keep the candidate with
 // the smaller residual in x and its matvec slots in qbuf (ties keep the
-// snapshot prediction).
+// primary).  which = 0 records the result in cand_rr / cand_pick (learned
+// candidate), 1 in guard_rr / guard_pick (Adams-Bashforth against the map).
 void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, double* part);
 void launch_cand_select(hipStream_t s, const DevNodes& N, const double* part_s, const double* part_l, double* x,
-                        const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc);
+                        const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc,
+                        int which = 0);
+// *out = sum of the g = res_grid(n) partials, in the fixed order of the solver's reductions.
+void launch_sum_partials(hipStream_t s, const double* part, int g, double* out);
 void launch_fill(hipStream_t s, int64_t n, double value, double* p);
 void launch_mlp_infer_array(hipStream_t s, const uint16_t* w, int64_t n, const float* x, float* y);
 void launch_mlp_infer_state(hipStream_t s, const uint16_t* w, const MlpState& S, int64_t n);

@@ -1041,8 +1041,8 @@ void launch_msum(hipStream_t s, const DevNodes& N, const double* qbuf, double* m
 __global__ __launch_bounds__(256) void k_cand_res(DevNodes N, const double* qbuf, const double* b, double* part) {
     double v = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
-        double q0, q1, q2;
-        gather_q(N, qbuf, n, q0, q1, q2);
+        double q0 = 0.0, q1 = 0.0, q2 = 0.0;
+        if (qbuf) gather_q(N, qbuf, n, q0, q1, q2);
         const uint8_t fm = N.fixmask[n];
         const double r0 = (fm & 1) ? 0.0 : b[3 * n] - q0;
         const double r1 = (fm & 2) ? 0.0 : b[3 * n + 1] - q1;
@@ -1059,16 +1059,18 @@ void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const
 
 __global__ __launch_bounds__(256) void k_cand_select(DevNodes N, const double* part_s, const double* part_l, int g,
                                                      double* x, const double* x_alt, double* qbuf,
-                                                     const double* qbuf_alt, int64_t nq, DevScalars* sc) {
+                                                     const double* qbuf_alt, int64_t nq, DevScalars* sc, int which) {
     double rs = lane_partials<kMaxResGrid / 256>(part_s, g, threadIdx.x, 256);
     double rl = lane_partials<kMaxResGrid / 256>(part_l, g, threadIdx.x, 256);
     rs = block_bcast_sum(rs);
     rl = block_bcast_sum(rl);
-    const bool pick = rl < rs;   // NaN in the learned candidate keeps the snapshot prediction
+    const bool pick = rl < rs;   // NaN in the alternative keeps the primary candidate
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->cand_rr[0] = rs;
-        sc->cand_rr[1] = rl;
-        sc->cand_pick = pick ? 1 : 0;
+        double* rr = which ? sc->guard_rr : sc->cand_rr;
+        rr[0] = rs;
+        rr[1] = rl;
+        if (which) sc->guard_pick = pick ? 1 : 0;
+        else sc->cand_pick = pick ? 1 : 0;
     }
     if (!pick) return;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1077,10 +1079,21 @@ __global__ __launch_bounds__(256) void k_cand_select(DevNodes N, const double* p
 }
 
 void launch_cand_select(hipStream_t s, const DevNodes& N, const double* part_s, const double* part_l, double* x,
-                        const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc) {
+                        const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc,
+                        int which) {
     const int g = res_grid(N.n);
     hipLaunchKernelGGL(k_cand_select, dim3(g), dim3(256), 0, s, N, part_s, part_l, g, x, x_alt, qbuf, qbuf_alt, nq,
-                       sc);
+                       sc, which);
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* part, int g, double* out) {
+    double v = lane_partials<kMaxResGrid / 256>(part, g, threadIdx.x, 256);
+    v = block_bcast_sum(v);
+    if (threadIdx.x == 0) *out = v;
+}
+
+void launch_sum_partials(hipStream_t s, const double* part, int g, double* out) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, g, out);
 }
 
 __global__ void k_fill(int64_t n, double value, double* p) {
@@ -1230,10 +1243,12 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // perform the same operations in the same order as a row-by-row
 // implementation (the back substitution reads R^T from one LDS copy).
 __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, const int32_t* region_chunk, int s, double drop,
-                                                 double* coef) {
+                                                 double* coef, const int32_t* region_case, const int32_t* case_lo) {
     __shared__ double R[32][33];
     const int r = blockIdx.x, lane = threadIdx.x;
-    const bool col = lane < s;
+    // columns before lo are left out: zero in the Gram, never kept, zero coefficients
+    const int lo = case_lo ? case_lo[region_case[r]] : 0;
+    const bool col = lane >= lo && lane < s;
     double g[32], y = 0.0, gll = 0.0;   // g[i] = G[i][lane]; gll = G[lane][lane], summed in the same order
 #pragma unroll
     for (int i = 0; i < 32; ++i) g[i] = 0.0;
@@ -1296,12 +1311,13 @@ __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, const int32_t
 }
 
 void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double drop, double* gh,
-                       double* coef) {
+                       double* coef, const int32_t* case_lo) {
     if (s_eff <= 16)
         hipLaunchKernelGGL(k_gram<1>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
     else
         hipLaunchKernelGGL(k_gram<2>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
-    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(64), 0, s, gh, C.first, s_eff, drop, coef);
+    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(64), 0, s, gh, C.first, s_eff, drop, coef, C.region_case,
+                       case_lo);
 }
 
 // x = dab + sum_j coef_j Y_j on each node chunk with its region's

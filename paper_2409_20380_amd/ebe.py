@@ -35,7 +35,8 @@ class Config(C.Structure):
                 ("tol", C.c_double), ("drop_tol", C.c_double), ("inner_tol", C.c_double), ("max_iter", C.c_int32),
                 ("s", C.c_int32), ("predictor", C.c_int32), ("region_nodes", C.c_int32),
                 ("patch_elems", C.c_int32), ("chunk_iters", C.c_int32), ("precision", C.c_int32),
-                ("inner_iters", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("inner_iters", C.c_int32), ("s_min", C.c_int32), ("fixed_window", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class SolveStats(C.Structure):
@@ -46,13 +47,21 @@ class SolveStats(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("it", C.c_int32), ("s_eff", C.c_int32), ("iters", C.c_int32), ("restarts", C.c_int32),
                 ("status", C.c_int32), ("inner_iters", C.c_int32), ("res0", C.c_double), ("res_rec", C.c_double),
-                ("res_true", C.c_double), ("bnorm", C.c_double), ("learned", C.c_int32), ("reserved", C.c_int32),
-                ("res0_snapshot", C.c_double), ("res0_learned", C.c_double)]
+                ("res_true", C.c_double), ("bnorm", C.c_double), ("learned", C.c_int32), ("first", C.c_int32),
+                ("res0_snapshot", C.c_double), ("res0_learned", C.c_double), ("map_kept", C.c_int32),
+                ("reserved", C.c_int32), ("res0_map", C.c_double), ("res0_ab", C.c_double)]
+
+
+class PredStats(C.Structure):
+    _fields_ = [("s_eff", C.c_int32), ("first", C.c_int32), ("map_kept", C.c_int32), ("learned", C.c_int32),
+                ("res0", C.c_double), ("res0_map", C.c_double), ("res0_ab", C.c_double),
+                ("res0_learned", C.c_double), ("bnorm", C.c_double)]
 
 
 class BatchStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("s_eff", C.c_int32),
-                ("res0", C.c_double), ("res_true", C.c_double), ("bnorm", C.c_double)]
+                ("res0", C.c_double), ("res_true", C.c_double), ("bnorm", C.c_double), ("first", C.c_int32),
+                ("map_kept", C.c_int32)]
 
 
 # Every symbol include/ebe.h declares (checked by the CPU test suite).
@@ -93,13 +102,13 @@ def lib():
     L.ebe_apply_mk.argtypes = [vp, C.c_double, C.c_double, vp, vp]
     L.ebe_precond.argtypes = [vp, vp, vp]
     L.ebe_rhs.argtypes = [vp, vp, d_p, vp]
-    L.ebe_predict.argtypes = [vp, vp, vp, i32_p]
+    L.ebe_predict.argtypes = [vp, vp, d_p, vp, vp]
     L.ebe_refine.argtypes = [vp, vp, vp, C.POINTER(SolveStats)]
     L.ebe_step.argtypes = [vp, vp, d_p, C.POINTER(StepStats)]
     L.ebe_get_state.argtypes = [vp, vp, vp, vp]
     L.ebe_set_state.argtypes = [vp, vp, vp, vp]
-    L.ebe_get_history.argtypes = [vp, vp, vp, i32_p]
-    L.ebe_set_history.argtypes = [vp, vp, vp, C.c_int32]
+    L.ebe_get_history.argtypes = [vp, vp, vp, i32_p, i32_p]
+    L.ebe_set_history.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
     L.ebe_sync.argtypes = [vp]
     L.ebe_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.ebe_kernel_time.argtypes = [vp, i64_p, d_p]
@@ -182,13 +191,13 @@ class Solver:
 
     def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
                  max_iter=10000, drop_tol=0.0, region_nodes=512, patch_elems=256, chunk_iters=0, precision=PREC_FP64,
-                 inner_iters=0, inner_tol=0.0, stream=None):
+                 inner_iters=0, inner_tol=0.0, s_min=0, fixed_window=False, stream=None):
         import torch
         L = lib()
         cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol,
                      drop_tol=drop_tol, max_iter=max_iter, s=s, predictor=predictor, region_nodes=region_nodes,
                      patch_elems=patch_elems, chunk_iters=chunk_iters, precision=precision,
-                     inner_iters=inner_iters, inner_tol=inner_tol)
+                     inner_iters=inner_iters, inner_tol=inner_tol, s_min=s_min, fixed_window=int(bool(fixed_window)))
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -264,11 +273,13 @@ class Solver:
         self._check(lib().ebe_rhs(self._h, _dev(f_ext), g, _dev(b)))
         return b
 
-    def predict(self, f_next=None, out=None):
+    def predict(self, f_next=None, base_acc=None, out=None, stats=True):
+        """Guess of the next step's increment; returns (x, PredStats or None)."""
         x = self._out(out)
-        se = C.c_int32()
-        self._check(lib().ebe_predict(self._h, _dev(f_next), _dev(x), C.byref(se)))
-        return x, se.value
+        st = PredStats() if stats else None
+        g = None if base_acc is None else (C.c_double * 3)(*[float(v) for v in base_acc])
+        self._check(lib().ebe_predict(self._h, _dev(f_next), g, _dev(x), C.byref(st) if stats else None))
+        return x, st
 
     def refine(self, b, x):
         st = SolveStats()
@@ -297,12 +308,13 @@ class Solver:
         vh = torch.empty(4 * self.n3, dtype=torch.float64, device="cuda")
         ring = torch.empty((self.cfg.s + 1) * self.n3, dtype=torch.float64, device="cuda")
         it = C.c_int32()
-        self._check(lib().ebe_get_history(self._h, _dev(vh), _dev(ring), C.byref(it)))
-        return vh.view(4, self.n3), ring.view(self.cfg.s + 1, self.n3), it.value
+        win = C.c_int32()
+        self._check(lib().ebe_get_history(self._h, _dev(vh), _dev(ring), C.byref(it), C.byref(win)))
+        return vh.view(4, self.n3), ring.view(self.cfg.s + 1, self.n3), it.value, win.value
 
-    def set_history(self, vhist, ring, it):
+    def set_history(self, vhist, ring, it, win=1):
         self._check(lib().ebe_set_history(self._h, _dev(vhist.contiguous().view(-1)),
-                                          _dev(ring.contiguous().view(-1)), int(it)))
+                                          _dev(ring.contiguous().view(-1)), int(it), int(win)))
 
     def sync(self):
         self._check(lib().ebe_sync(self._h))

@@ -81,11 +81,11 @@ def _oracle_traj(model, m, wave, nt, tol, oracle_lib, s=6):
     wl = SMALL
     aR, bR = wl.rayleigh
     st = oracle_lib.Stepper(model, wl.dt, aR, bR, s=s, kind=2, tol=tol, regions=m["regions"])
-    U, its = [], []
+    U, its, dec = [], [], []
     for it in range(1, nt + 1):
         rec, _, _ = st.step(g=wave[it])
-        U.append(st.u.copy()); its.append(rec.iters)
-    return np.array(U), np.array(its)
+        U.append(st.u.copy()); its.append(rec.iters); dec.append((rec.s_eff, rec.first, rec.pick))
+    return np.array(U), np.array(its), dec
 
 
 def test_batch_trajectories_match_oracle(ms, models, oracle_lib):
@@ -98,22 +98,27 @@ def test_batch_trajectories_match_oracle(ms, models, oracle_lib):
     C = sum(m["r"] for m in ms)
     waves = _waves(C, nt, SMALL.dt, 1)
     U = [[] for _ in range(C)]
+    dec = [[] for _ in range(C)]
     its = np.zeros((nt, C), dtype=int)
     for it in range(1, nt + 1):
         st = b.step(np.array([w[it] for w in waves]))
         for c in range(C):
             assert st[c].status == 0 and st[c].res_true < SMALL.tol, (it, c, st[c].res_true)
             its[it - 1, c] = st[c].iters
+            dec[c].append((st[c].s_eff, st[c].first, st[c].map_kept))
             U[c].append(to_host(b.get_state(c)[0]))
     c = 0
     for m, model in zip(ms, models):
         for k in range(m["r"]):
-            Uref, _ = _oracle_traj(model, m, waves[c], nt, 1e-13, oracle_lib)
-            _, its8 = _oracle_traj(model, m, waves[c], nt, SMALL.tol, oracle_lib)
+            Uref, _, _ = _oracle_traj(model, m, waves[c], nt, 1e-13, oracle_lib)
+            _, its8, dec8 = _oracle_traj(model, m, waves[c], nt, SMALL.tol, oracle_lib)
             err = np.linalg.norm(np.array(U[c]) - Uref) / np.linalg.norm(Uref)
             say(f"case {c}: space-time rel L2 {err:.2e}; iters {its[:, c].mean():.2f} vs oracle {its8.mean():.2f}")
+            say(f"case {c}: window decisions {dec[c]}")
             assert err < TRAJ_TOL
             assert np.abs(its[:, c] - its8).max() <= 3
+            # each case's guarded window takes the oracle's decisions
+            assert dec[c] == dec8
             c += 1
     b.close()
 

@@ -329,6 +329,19 @@ int ebe_mlp_forward(ebe_handle* h, int64_t n, const float* x, float* y);
 /* Loss and gradient over n (1..8192) samples: x device [n][15], t device
  * [n][3] (scaled targets); grad device [5379] out; loss host out or NULL. */
 int ebe_mlp_grad(ebe_handle* h, int64_t n, const float* x, const float* t, float* grad, double* loss);
+/* For callers that cannot allocate device memory during a call (code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * allocation): the result of ebe_mlp_grad (same kernels, same gradient and
+ * loss) with the training activations and partial sums in a fixed device
+ * array of the library (about 13 MB per GPU, held until the process ends)
+ * instead of buffers the handle allocates when n first exceeds its capacity.
+ * n must be in 1..8192, the array's capacity (EBE_E_INVALID_ARG otherwise);
+ * the weights must be set (EBE_E_BAD_STATE otherwise).  grad device [5379]
+ * out.  loss: host out, or NULL -- then the call only enqueues kernels on the
+ * handle's stream (no copy, no synchronisation).  All calls on one GPU share
+ * the one array: calls that overlap in time on that GPU (other streams,
+ * threads or handles) race and give wrong results. */
+int ebe_mlp_grad_noalloc(ebe_handle* h, int64_t n, const float* x, const float* t, float* grad, double* loss);
 /* One Adam step of the master weights with the given gradient (device [5379]). */
 int ebe_mlp_adam(ebe_handle* h, const float* grad, float lr);
 /* Sample collection: every later ebe_step from step 5 on appends one sample

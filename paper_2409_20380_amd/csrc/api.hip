@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +40,45 @@ struct State {
 };
 
 thread_local std::string g_create_error;
+
+// ---- fixed device array of ebe_mlp_grad_noalloc ---------------------------
+// Training activations of one gradient evaluation of at most kMlpMaxBatch
+// samples, laid out as 256-byte aligned pieces: the loss (one double), the
+// per-workgroup loss partials, then X [15][B], Z1, H1, Z2, H2 [64][B],
+// dY [3][B], dZ1, dZ2 [64][B] (B = the call's sample count, at most
+// kMlpMaxBatch, so every piece is sized for kMlpMaxBatch).
+constexpr size_t kScratchAlign = 256;
+constexpr size_t scratch_piece(size_t bytes) { return (bytes + kScratchAlign - 1) / kScratchAlign * kScratchAlign; }
+constexpr size_t kScratchLoss = 0;
+constexpr size_t kScratchLossPart = kScratchLoss + scratch_piece(sizeof(double));
+constexpr size_t kScratchAct = kScratchLossPart + scratch_piece(sizeof(float) * (kMlpMaxBatch + 255) / 256);
+constexpr size_t kScratchFloatsPerSample = kMlpIn + 4 * kMlpHid + kMlpOut + 2 * kMlpHid;
+constexpr size_t kScratchBytes = kScratchAct + scratch_piece(sizeof(float) * kScratchFloatsPerSample * kMlpMaxBatch);
+static_assert(kScratchBytes < 14u * 1024 * 1024, "the fixed training scratch stays modest");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` on each device (its host-side name is not a
+// device address).  Looked up once per device, with that device current, by
+// ebe_create.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t lookup_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_scratch_ptr[device] = ptr;
+    return e;
+}
+
+void* scratch_ptr(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+}
 
 }  // namespace
 
@@ -677,6 +717,11 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
         delete h;
         return EBE_E_HIP;
     }
+    if (hipError_t e = lookup_scratch(h->device); e != hipSuccess) {
+        g_create_error = std::string("device address of the fixed scratch array: ") + hipGetErrorString(e);
+        delete h;
+        return EBE_E_HIP;
+    }
     h->cM = 4.0 / (c.dt * c.dt) + 2.0 * c.rayleigh_alpha / c.dt;
     h->cK = 1.0 + 2.0 * c.rayleigh_beta / c.dt;
     *out = h;
@@ -1192,6 +1237,45 @@ int ebe_mlp_grad(ebe_handle* h, int64_t n, const float* x, const float* t, float
         HIPCHK(hipMemcpyAsync(&l, h->tr_loss, sizeof(double), hipMemcpyDeviceToHost, h->stream));
         sync_stream(h);
         if (loss) *loss = l;
+        return EBE_OK;
+    });
+}
+
+int ebe_mlp_grad_noalloc(ebe_handle* h, int64_t n, const float* x, const float* t, float* grad, double* loss) {
+    return guarded(h, [&]() -> int {
+        need_ready(h);
+        if (n < 1 || n > kMlpMaxBatch) throw Arg{"n must be in 1..8192 (the fixed scratch array's capacity)"};
+        need_ptr(x, "x");
+        need_ptr(t, "t");
+        need_ptr(grad, "grad");
+        unsigned char* base = static_cast<unsigned char*>(scratch_ptr(h->device));
+        if (!base) throw State{"no device address of the fixed scratch array on this device"};
+        const size_t B = (size_t)n;
+        float* act = reinterpret_cast<float*>(base + kScratchAct);
+        MlpTrain T = h->tr;   // weights, master weights and moments of the handle; no training buffers
+        T.x_in = x;
+        T.t_in = t;
+        T.X = act;
+        T.Z1 = T.X + kMlpIn * B;
+        T.H1 = T.Z1 + kMlpHid * B;
+        T.Z2 = T.H1 + kMlpHid * B;
+        T.H2 = T.Z2 + kMlpHid * B;
+        T.dY = T.H2 + kMlpHid * B;
+        T.dZ1 = T.dY + kMlpOut * B;
+        T.dZ2 = T.dZ1 + kMlpHid * B;
+        T.loss_part = reinterpret_cast<float*>(base + kScratchLossPart);
+        T.grad = grad;        // every entry is written by the weight-gradient kernels
+        launch_mlp_grads(h->stream, T, (int)n, nullptr);
+        if (loss) {
+            double* dloss = reinterpret_cast<double*>(base + kScratchLoss);
+            launch_mlp_loss(h->stream, T, (int)n, dloss);
+            check_launch();
+            double l = 0.0;
+            HIPCHK(hipMemcpyAsync(&l, dloss, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            sync_stream(h);
+            *loss = l;
+        }
+        check_launch();
         return EBE_OK;
     });
 }

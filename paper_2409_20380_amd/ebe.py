@@ -69,7 +69,7 @@ EXPORTS = ("ebe_version", "ebe_create", "ebe_destroy", "ebe_last_error", "ebe_as
            "ebe_apply", "ebe_apply_mk", "ebe_precond", "ebe_rhs", "ebe_predict", "ebe_refine", "ebe_step",
            "ebe_get_state", "ebe_set_state", "ebe_get_history", "ebe_set_history", "ebe_sync",
            "ebe_set_kernel_timing", "ebe_kernel_time", "ebe_sizes", "ebe_get_config", "ebe_set_predictor",
-           "ebe_reset", "ebe_mlp_set", "ebe_mlp_get", "ebe_mlp_forward", "ebe_mlp_grad", "ebe_mlp_adam",
+           "ebe_reset", "ebe_mlp_set", "ebe_mlp_get", "ebe_mlp_forward", "ebe_mlp_grad", "ebe_mlp_grad_noalloc", "ebe_mlp_adam",
            "ebe_collect", "ebe_samples", "ebe_mlp_fit_scales", "ebe_mlp_train", "ebe_batch_create",
            "ebe_batch_destroy", "ebe_batch_last_error", "ebe_batch_add_mesh", "ebe_batch_set_group_config",
            "ebe_batch_assemble", "ebe_batch_group_info", "ebe_batch_use_graph", "ebe_batch_reset", "ebe_batch_apply",
@@ -121,6 +121,7 @@ def lib():
     L.ebe_mlp_get.argtypes = [vp, f_p, f_p]
     L.ebe_mlp_forward.argtypes = [vp, C.c_int64, vp, vp]
     L.ebe_mlp_grad.argtypes = [vp, C.c_int64, vp, vp, vp, d_p]
+    L.ebe_mlp_grad_noalloc.argtypes = [vp, C.c_int64, vp, vp, vp, d_p]
     L.ebe_mlp_adam.argtypes = [vp, vp, C.c_float]
     L.ebe_collect.argtypes = [vp, C.c_int64, vp, C.c_int32]
     L.ebe_samples.argtypes = [vp, i64_p, vp]
@@ -372,6 +373,18 @@ class Solver:
         self._check(lib().ebe_mlp_grad(self._h, n, _devt(x, "float32", n * MLP_IN), _devt(t, "float32", n * MLP_OUT),
                                        _devt(g, "float32"), C.byref(loss)))
         return g, loss.value
+
+    def mlp_grad_noalloc(self, x, t, out=None, want_loss=True):
+        """ebe_mlp_grad_noalloc: the library allocates nothing during the call (out: the caller's
+        float32 [5379] device tensor, or one allocated here before the call)."""
+        import torch
+        n = x.shape[0]
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device="cuda") if out is None else out
+        loss = C.c_double()
+        self._check(lib().ebe_mlp_grad_noalloc(self._h, n, _devt(x, "float32", n * MLP_IN),
+                                               _devt(t, "float32", n * MLP_OUT), _devt(g, "float32", MLP_PARAMS),
+                                               C.byref(loss) if want_loss else None))
+        return g, (loss.value if want_loss else None)
 
     def mlp_adam(self, grad, lr):
         self._check(lib().ebe_mlp_adam(self._h, _devt(grad, "float32", MLP_PARAMS), float(lr)))

@@ -151,6 +151,15 @@ def main():
     ap.add_argument("--drop-tol", type=float, default=0.0,
                     help="predictor column drop threshold (0: the library's, 1e-6 for fp64 and 1e-5 for the mixed "
                          "forms, whose FP32 inner solves leave rounding noise in the snapshots)")
+    ap.add_argument("--predictor", type=int, choices=[0, 1, 2], default=2,
+                    help="plain/large: guess of each step (0 zero, 1 AB4, 2 AB4 + regional snapshot map)")
+    ap.add_argument("--snapshots", type=int, default=0, help="plain/large: snapshot window s (0: the workload's, 32)")
+    ap.add_argument("--s-min", type=int, default=0,
+                    help="plain/large: column pairs before the map is used (0: the library's, 8)")
+    ap.add_argument("--fixed-window", action="store_true",
+                    help="plain/large: the map's guess always, the window never restarts (no AB4 guard)")
+    ap.add_argument("--input", choices=["base", "surface"], default="base",
+                    help="plain/large: base acceleration (default) or the paper-like surface impulses")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the steps, copy a buffer of this many MiB device-to-device once (counter calibration)")
     args = ap.parse_args()
@@ -177,14 +186,28 @@ def main():
     wl = inputs.WORKLOADS[args.workload]
     prec = {"fp64": ebe.PREC_FP64, "fp32": ebe.PREC_FP32, "bf16": ebe.PREC_BF16}[args.precision]
     nt = args.warmup + args.steps
-    wl_run = inputs.Workload(wl.name, cells=wl.cells, h=wl.h, dt=wl.dt, nt=nt, s=wl.s, tol=wl.tol,
+    s_win = args.snapshots or wl.s
+    wl_run = inputs.Workload(wl.name, cells=wl.cells, h=wl.h, dt=wl.dt, nt=nt, s=s_win, tol=wl.tol,
                              seed=wl.seed, region_block=args.region_block or wl.region_block)
     mesh, em, mat, fx, regions, wave = wl_run.build()
     dof = 3 * mesh.n_nodes
     log(f"mesh {wl.cells}: {mesh.n_nodes} nodes, {dof} dof, {mesh.n_elems} elements")
     aR, bR = wl.rayleigh
-    sol = ebe.Solver(wl.dt, aR, bR, s=wl.s, tol=wl.tol, patch_elems=args.patch_elems, precision=prec,
-                     inner_iters=args.inner_iters, inner_tol=args.inner_tol, drop_tol=args.drop_tol)
+    sol = ebe.Solver(wl.dt, aR, bR, s=s_win, tol=wl.tol, patch_elems=args.patch_elems, precision=prec,
+                     inner_iters=args.inner_iters, inner_tol=args.inner_tol, drop_tol=args.drop_tol,
+                     predictor=args.predictor, s_min=args.s_min, fixed_window=args.fixed_window)
+    # per-step forcing, resident in HBM before the timed region: base acceleration (3 values
+    # a step) or the paper-like surface impulses (a force vector a step)
+    f_all = None
+    if args.input == "surface":
+        sp_nodes, sp_force = inputs.surface_impulses(mesh, wl.seed, nt, wl.dt)
+        f_all = torch.zeros((nt + 1, mesh.n_nodes, 3), dtype=torch.float64, device="cuda")
+        f_all[:, torch.from_numpy(sp_nodes.astype(np.int64)).cuda()] = torch.from_numpy(sp_force).cuda()
+        f_all = f_all.view(nt + 1, dof)
+        log(f"surface impulses at {sp_nodes.size} top nodes")
+
+    def forcing(it):
+        return (None, wave[it]) if f_all is None else (f_all[it], None)
     drop = sol.effective_config().drop_tol
     t0 = time.time()
     sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
@@ -201,19 +224,24 @@ def main():
         del src, dst
 
     for it in range(1, args.warmup + 1):
-        st = sol.step(base_acc=wave[it])
+        f, g = forcing(it)
+        st = sol.step(f_ext=f, base_acc=g)
         if it % 50 == 0 or it == args.warmup:
             log(f"warmup step {it}: {st.iters} iters, res_true {st.res_true:.2e}")
 
     sol.set_kernel_timing(args.timing_every)
-    iters, res, inner = [], [], []
+    iters, res, inner, res0, s_eff, kept = [], [], [], [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for it in range(args.warmup + 1, nt + 1):
-        st = sol.step(base_acc=wave[it])
+        f, g = forcing(it)
+        st = sol.step(f_ext=f, base_acc=g)
         iters.append(st.iters)
         inner.append(st.inner_iters)
         res.append(st.res_true)
+        res0.append(st.res0)
+        s_eff.append(st.s_eff)
+        kept.append(st.map_kept)
         if st.status != 0:
             raise RuntimeError(f"step {it} did not converge")
     torch.cuda.synchronize()
@@ -246,8 +274,13 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else f"f64 outer / {args.precision} inner",
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": list(wl.cells), "nodes": mesh.n_nodes, "dof": dof,
-                   "elements": mesh.n_elems, "dt": wl.dt, "snapshots": wl.s, "tol": wl.tol,
-                   "predictor": "AB4 + regional snapshot map", "region_nodes": wl_run.region_block ** 3,
+                   "elements": mesh.n_elems, "dt": wl.dt, "snapshots": s_win, "tol": wl.tol,
+                   "predictor": {0: "zero guess", 1: "AB4",
+                                 2: "AB4 + regional snapshot map" + (", fixed window" if args.fixed_window else
+                                                                     ", guarded window")}[args.predictor],
+                   "s_min": ecfg.s_min, "input": ("base acceleration" if args.input == "base" else
+                                                  "surface impulses (284 points)"),
+                   "region_nodes": wl_run.region_block ** 3,
                    "drop_tol": drop,
                    "timed_steps": f"{args.warmup + 1}-{nt}",
                    "refine": ("block-Jacobi PCG, FP64" if args.precision == "fp64" else
@@ -256,6 +289,10 @@ def main():
         "cg_iters_per_step": float(np.mean(iters)),
         "inner_iters_per_step": float(np.mean(inner)),
         "cg_iters_min_max": [int(np.min(iters)), int(np.max(iters))],
+        "initial_rel_residual_geomean": float(np.exp(np.mean(np.log(np.maximum(res0, 1e-300))))),
+        "snapshot_pairs_mean": float(np.mean(s_eff)),
+        "map_kept_steps": int(sum(1 for k in kept if k == 1)),
+        "window_restarts": int(sum(1 for k in kept if k == 0)),
         "max_true_rel_residual": float(np.max(res)),
         "ebe_matvec_hbm_gbs": achieved,
         "roofline": {"kernel": "k_ebe<PCG> (fused direction update + EBE matvec + (p,Ap))",
@@ -265,7 +302,8 @@ def main():
                      "bytes_per_launch": launch_bytes, "mean_launch_ms": ebe_ms, "timed_launches": n_timed},
     }
     sol.close()
-    if not args.no_cpu_baseline and args.workload == "plain":
+    if not args.no_cpu_baseline and args.workload == "plain" and args.input == "base" and args.predictor == 2 \
+            and not args.snapshots and not args.s_min and not args.fixed_window:
         log(f"CPU baseline: oracle, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(wl_run, mesh, em, mat, fx, regions, wave, args.cpu_steps,
                                            gpu_iters=float(np.mean(iters)))

@@ -191,6 +191,44 @@ def base_wave(seed: int, nt: int, dt: float, f_lo: float = 0.1, f_hi: float = 2.
     return out
 
 
+def surface_impulses(mesh: BoxMesh, seed: int, nt: int, dt: float, n_points: int = 284,
+                     f_lo: float = 0.1, f_hi: float = 2.5, onset_s: float = 0.5, ng: int = 8192):
+    """Paper-like point forces: impulses with random amplitudes and flat spectra in
+    random directions at randomly chosen points of the ground surface, after which
+    the body vibrates freely (the paper's application, Sec. 3.1).
+
+    n_points distinct top-surface nodes (284 keeps the paper's 10,000 points per
+    950 x 950 m of surface on a 160 x 160 m top); each gets a unit impulse
+    band-passed to [f_lo, f_hi] Hz (flat amplitude spectrum in the band), centred
+    at 1 s plus a uniform random onset in [0, onset_s] s and windowed by a
+    Gaussian of 0.4 s standard deviation (so the pulse has decayed before t = 0
+    and ends within about 3 s), times a standard-normal amplitude, along a
+    uniformly random unit direction.  Returns (nodes int32 [K], force float64
+    [nt + 1][K][3], t = 0, dt, ...); force 0 at t = 0 by a sin^2 taper over 0.2 s.
+    """
+    rng = np.random.default_rng([seed, 6007])
+    top = np.where(mesh.lattice[:, 2] == 2 * mesh.nz)[0]
+    k = min(n_points, top.size)
+    nodes = np.sort(rng.choice(top, size=k, replace=False)).astype(np.int32)
+    amp = rng.standard_normal(k)
+    d = rng.standard_normal((k, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    onset = 1.0 + rng.uniform(0.0, onset_s, size=k)
+    n = max(ng, nt + 1)
+    freqs = np.fft.rfftfreq(n, d=dt)
+    band = (freqs >= f_lo) & (freqs <= f_hi)
+    t = np.arange(nt + 1) * dt
+    ramp = np.where(t < 0.2, np.sin(0.5 * np.pi * np.clip(t / 0.2, 0, 1)) ** 2, 1.0)
+    tt = np.arange(n) * dt
+    force = np.zeros((nt + 1, k, 3))
+    for p in range(k):
+        spec = np.where(band, np.exp(-2j * np.pi * freqs * onset[p]), 0.0)
+        pulse = np.fft.irfft(spec, n=n) * np.exp(-0.5 * ((tt - onset[p]) / 0.4) ** 2)
+        pulse /= np.abs(pulse).max()
+        force[:, p, :] = (amp[p] * pulse[: nt + 1] * ramp)[:, None] * d[p][None, :]
+    return nodes, force
+
+
 def random_vector(seed: int, n: int) -> np.ndarray:
     """Seeded standard-normal float64 vector (parity-test operand)."""
     return np.random.default_rng([seed, 7919]).standard_normal(n)

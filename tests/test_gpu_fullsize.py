@@ -1,0 +1,130 @@
+"""Full-size parity: the 64x64x32-cell mesh (1,081,665 nodes, 3,244,995 dof) and the
+largest ensemble mesh (48x48x24 cells) against the FP64 oracle, in the launch
+configurations the bench times (persistent multi-patch PCG walk with the XCD-aware
+patch order, 1024-partial reductions, tuned batched element passes).  Needs an
+MI355X; the oracle runs on the host cores (about a minute per test).
+
+Bars (Sec. 3.1, Eq. GE:DIS, Algorithm 1): right-hand side within 1e-12 over the whole
+vector; trajectories within 1e-6 space-time relative L2 of the oracle at 1e-13,
+true relative residual below 1e-8 on every step, trips within 2 of the oracle's at
+1e-8 with the same window decisions.
+"""
+import numpy as np
+import pytest
+
+from paper_2409_20380_amd import inputs
+from tests.gpu_common import cm_ck, rel_max, to_dev, to_host
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+TRAJ_TOL = 1e-6
+STEPS = 10
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _build(wl, oracle_lib):
+    mesh, em, mat, fx, regions, wave = wl.build()
+    aR, bR = wl.rayleigh
+    cM, cK = cm_ck(wl.dt, aR, bR)
+    model = oracle_lib.Model(mesh.coords, mesh.conn, em, mat, fx, cM, cK)
+    return dict(mesh=mesh, em=em, mat=mat, fx=fx, regions=regions, wave=wave, aR=aR, bR=bR, model=model, wl=wl)
+
+
+def _oracle_steps(c, oracle_lib, tol, nt, wave):
+    wl = c["wl"]
+    st = oracle_lib.Stepper(c["model"], wl.dt, c["aR"], c["bR"], s=wl.s, kind=2, tol=tol, regions=c["regions"])
+    U, its, dec = [], [], []
+    for it in range(1, nt + 1):
+        rec, _, _ = st.step(g=wave[it])
+        U.append(st.u.copy()); its.append(rec.iters); dec.append((rec.s_eff, rec.first, rec.pick))
+    return np.array(U), np.array(its), dec
+
+
+def test_headline_mesh_rhs_and_steps_match_oracle(oracle_lib):
+    from paper_2409_20380_amd import ebe
+    wl = inputs.PLAIN
+    say("full size: build", wl.cells, "(oracle assembly ~30 s)")
+    c = _build(wl, oracle_lib)
+    m, fx = c["model"], c["fx"]
+    sol = ebe.Solver(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol)
+    sol.assemble(c["mesh"].coords, c["mesh"].conn, c["em"], c["mat"], fx, c["regions"])
+    # right-hand side of a seeded state over the whole vector (dual-operand element pass)
+    say("full size: rhs")
+    free = fx.ravel() == 0
+    u, v, a, f = (inputs.random_vector(60 + k, m.n3) for k in range(4))
+    for vec in (u, v, a):
+        vec[~free] = 0.0
+    g = np.array([0.2, -0.7, 1.1])
+    sol.set_state(to_dev(u), to_dev(v), to_dev(a))
+    b = to_host(sol.rhs(to_dev(f), g))
+    ref = m.rhs(u, v, a, wl.dt, c["aR"], c["bR"], g=g, f_add=f)
+    err_b = rel_max(b, ref)
+    say(f"full size: rhs max-abs rel error {err_b:.2e}")
+    assert err_b < 1e-12
+    sol.reset()
+    # ten steps from rest
+    say("full size:", STEPS, "steps on the GPU")
+    U, its, res, dg = [], [], [], []
+    for it in range(1, STEPS + 1):
+        st = sol.step(base_acc=c["wave"][it])
+        assert st.status == 0
+        U.append(to_host(sol.get_state()[0])); its.append(st.iters); res.append(st.res_true)
+        dg.append((st.s_eff, st.first, st.map_kept))
+    U, its, res = np.array(U), np.array(its), np.array(res)
+    say("full size: oracle at 1e-13 and at 1e-8")
+    Uref, _, _ = _oracle_steps(c, oracle_lib, 1e-13, STEPS, c["wave"])
+    _, its8, do = _oracle_steps(c, oracle_lib, wl.tol, STEPS, c["wave"])
+    err = np.linalg.norm(U - Uref) / np.linalg.norm(Uref)
+    say(f"full size: space-time rel L2 {err:.2e}; max true residual {res.max():.2e}; trips gpu {its.tolist()} "
+        f"oracle {its8.tolist()}; decisions {dg}")
+    assert err < TRAJ_TOL
+    assert (res < wl.tol).all()
+    assert np.abs(its - its8).max() <= 2
+    assert dg == do
+    sol.close()
+    # the FP32-inner form on the same steps, against the same tight oracle
+    say("full size: two steps with the FP32 inner solve")
+    mx = ebe.Solver(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol, precision=ebe.PREC_FP32)
+    mx.assemble(c["mesh"].coords, c["mesh"].conn, c["em"], c["mat"], fx, c["regions"])
+    Um = []
+    for it in range(1, 3):
+        st = mx.step(base_acc=c["wave"][it])
+        assert st.status == 0 and st.res_true < wl.tol
+        Um.append(to_host(mx.get_state()[0]))
+    err_m = np.linalg.norm(np.array(Um) - Uref[:2]) / np.linalg.norm(Uref[:2])
+    say(f"full size: FP32-inner space-time rel L2 vs tight oracle {err_m:.2e}")
+    assert err_m < TRAJ_TOL
+    mx.close()
+
+
+def test_largest_ensemble_mesh_cases_match_oracle(oracle_lib):
+    from paper_2409_20380_amd import ebe
+    cells, _ = inputs.ENSEMBLE[2]
+    r, nt = 2, 5
+    wl = inputs.Workload("ens_large", cells=cells, nt=nt, s=inputs.ENSEMBLE_S)
+    say("full-size ensemble group", cells, "cases", r, "steps", nt)
+    c = _build(wl, oracle_lib)
+    b = ebe.Batch(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol)
+    b.add_mesh(c["mesh"].coords, c["mesh"].conn, c["em"], c["mat"], c["fx"], c["regions"], r)
+    b.assemble(tune=True)
+    say("tuned", b.group_info(0))
+    waves = [inputs.base_wave(1 + k, nt, wl.dt) for k in range(r)]
+    U = [[] for _ in range(r)]
+    its = np.zeros((nt, r), dtype=int)
+    for it in range(1, nt + 1):
+        st = b.step(np.array([w[it] for w in waves]))
+        for k in range(r):
+            assert st[k].status == 0 and st[k].res_true < wl.tol, (it, k, st[k].res_true)
+            its[it - 1, k] = st[k].iters
+            U[k].append(to_host(b.get_state(k)[0]))
+    for k in range(r):
+        Uref, _, _ = _oracle_steps(c, oracle_lib, 1e-13, nt, waves[k])
+        _, its8, _ = _oracle_steps(c, oracle_lib, wl.tol, nt, waves[k])
+        err = np.linalg.norm(np.array(U[k]) - Uref) / np.linalg.norm(Uref)
+        say(f"case {k}: space-time rel L2 {err:.2e}; trips {its[:, k].tolist()} oracle {its8.tolist()}")
+        assert err < TRAJ_TOL
+        assert np.abs(its[:, k] - its8).max() <= 2
+    b.close()

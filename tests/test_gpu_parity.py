@@ -205,6 +205,87 @@ def test_predict_exact_recovery_in_snapshot_span(small_map):
     sol.set_history(vh0, ring0, it0, w0)
 
 
+def _window_ring(small, seed, it):
+    """Random free-dof ring and the slots of the window W = [e^{n-s-1} .. e^{n-1}] of step n = it + 1."""
+    m, wl = small["model"], small["wl"]
+    s = wl.s
+    rng = np.random.default_rng(seed)
+    ring = rng.standard_normal((s + 1, m.n3))
+    ring[:, small["fx"].ravel() == 1] = 0.0
+    n, S1 = it + 1, s + 1
+    cols = [(n - s - 1 + j - 1) % S1 for j in range(s + 1)]
+    return rng, ring, cols
+
+
+def _predict_on(small, ring, it):
+    sol = small["sol"]
+    vh0, ring0, it0, w0 = sol.get_history()
+    sol.set_history(to_dev(np.zeros((4, small["model"].n3))), to_dev(ring), it)
+    xg, ps = sol.predict()
+    sol.set_history(vh0, ring0, it0, w0)
+    return to_host(xg), ps
+
+
+def test_predict_dependent_columns_match_oracle(small_map, oracle_lib):
+    """Sec. 3.2's modified Gram-Schmidt with exactly dependent inputs: a duplicated
+    column and a scaled copy.  Both sides drop the later copy (its orthogonal part is
+    zero), so the prediction is the same least-squares map: equal to 1e-10."""
+    small = small_map
+    s, it = small["wl"].s, 30
+    say("predict with a duplicated and a scaled column")
+    rng, ring, cols = _window_ring(small, 41, it)
+    ring[cols[5]] = ring[cols[2]]             # duplicate of input 2
+    ring[cols[9]] = -2.5 * ring[cols[4]]      # scaled copy of input 4
+    xg, ps = _predict_on(small, ring, it)
+    W = [ring[c] for c in cols]
+    expect = oracle_lib.predict_regional(small["regions"], W[:s], W[1:], W[s])
+    assert ps.s_eff == s and np.isfinite(xg).all()
+    assert rel_max(xg, expect) < 1e-10
+
+
+@pytest.mark.parametrize("rho,kept", [(3e-6, True), (3e-7, False)])
+def test_predict_near_dependent_column_is_a_least_squares_minimiser(small_map, rho, kept):
+    """Input 6 = 3 x input 0 + a part orthogonal-ish of relative size rho, just above
+    (3e-6) or below (3e-7) the drop threshold 1e-6.  Near the threshold several answers
+    are correct (any minimiser over the kept columns), so the check is validity: the
+    coefficients, recovered per region from the prediction (input 0 is not an output,
+    so the outputs stay well conditioned), are finite, leave column 6 out when its
+    part is below the threshold, and give a residual ||X_K a - q|| within 1e-9 of the
+    least-squares minimum over the kept columns K (an SVD solve in FP64)."""
+    small = small_map
+    s, it = small["wl"].s, 30
+    say("predict with a near-dependent column, rho", rho)
+    rng, ring, cols = _window_ring(small, 42, it)
+    dof_region = np.repeat(small["regions"], 3)
+    free = small["fx"].ravel() == 0
+    c6 = 3.0 * ring[cols[0]]
+    for r in range(int(small["regions"].max()) + 1):
+        sel = (dof_region == r) & free
+        z = rng.standard_normal(sel.sum())
+        c6[sel] += rho * np.linalg.norm(c6[sel]) * z / np.linalg.norm(z)
+    ring[cols[6]] = c6
+    xg, ps = _predict_on(small, ring, it)
+    assert np.isfinite(xg).all()
+    W = [ring[c] for c in cols]
+    worst = 0.0
+    for r in range(int(small["regions"].max()) + 1):
+        sel = (dof_region == r) & free
+        X = np.stack([w[sel] for w in W[:s]], axis=1)
+        Y = np.stack([w[sel] for w in W[1:]], axis=1)
+        q = W[s][sel]
+        a, res, *_ = np.linalg.lstsq(Y, xg[sel], rcond=None)
+        assert np.linalg.norm(Y @ a - xg[sel]) <= 1e-10 * np.linalg.norm(xg[sel])   # a prediction Y a
+        K = [j for j in range(s) if kept or j != 6]
+        if not kept:
+            assert abs(a[6]) <= 1e-8 * np.abs(a).max()
+        a_star, *_ = np.linalg.lstsq(X[:, K], q, rcond=None)
+        r_gpu = np.linalg.norm(X[:, K] @ a[K] - q)
+        r_min = np.linalg.norm(X[:, K] @ a_star - q)
+        worst = max(worst, r_gpu / r_min - 1.0)
+    say(f"rho {rho}: worst relative excess of the least-squares residual {worst:.2e}")
+    assert worst <= 1e-9
+
+
 def _oracle_at(c, oracle_lib, vh, ring, it, win, u, v, a, **kw):
     """An oracle stepper holding the given state and history."""
     wl = c["wl"]

@@ -113,10 +113,21 @@ typedef struct {
                                paper's range 8 <= s <= 32, Sec. 4 / Fig. 3); AB4 alone before */
     int32_t fixed_window;   /* 0 (default): guarded window -- whenever the map is used, the
                                AB4 guess is evaluated too and kept when its initial residual
-                               is strictly smaller, and the window then restarts at that step
-                               (see "Snapshot window" below); 1: the map's guess is always
-                               used and the window never restarts */
-    int32_t reserved[2];
+                               is strictly smaller, and the window then restarts at that step;
+                               the window length adapts by probes (see "Snapshot window"
+                               below); 1: the map's guess is always used, over s column
+                               pairs, and the window never restarts */
+    int32_t probe_every;    /* guarded window: steps with a full window between two length
+                               probes (<= 0: 16) */
+    int32_t probe_step;     /* guarded window: column pairs a probe adds or removes (<= 0: 8) */
+    double skip_ratio;      /* guarded window: the AB4 guess is not evaluated while the map's
+                               initial residual is below skip_ratio x the last evaluated AB4
+                               one (0: 0.01; < 0: always evaluated) */
+    double col_cost;        /* guarded window: predictor cost of one window column, in PCG
+                               trips, against which the probes weigh the trips a longer window
+                               saves (0: 0.08, measured on the 64x64x32-cell mesh; < 0: no
+                               probes, the length stays s) */
+    int32_t reserved[4];
 } ebe_config;
 
 typedef struct {
@@ -145,10 +156,23 @@ typedef struct {
     double res0_learned;
     int32_t map_kept;       /* guarded window: 1 the map's guess was kept, 0 the AB4 guess
                                (the window restarted at this step); -1 no comparison */
-    int32_t reserved;
+    int32_t skipped;        /* guarded window: 1 if the AB4 guess was not evaluated (map far ahead) */
     double res0_map;        /* guarded window: ||b - A x||/||b|| of the map's and of the */
-    double res0_ab;         /* AB4 guess (free rows; 0 without a comparison) */
+    double res0_ab;         /* AB4 guess (free rows; 0 without a comparison or when skipped) */
+    int32_t probe;          /* window length probed this step (0: none) */
+    int32_t s_cap;          /* window length cap after this step */
+    double res0_probe;      /* ||b - A x||/||b|| of the guess over the probed length */
 } ebe_step_stats;
+
+/* Snapshot-window state carried from step to step (checkpoint / resume). */
+typedef struct {
+    int32_t start;          /* first step whose AB error may enter the window (>= 1) */
+    int32_t s_cap;          /* window length cap in column pairs (1..s; 0 on input: s) */
+    int32_t since;          /* steps with a full window since the last length probe */
+    int32_t grow_next;      /* direction of the next probe: 1 longer, 0 shorter */
+    double rho_ab;          /* last evaluated initial relative residual of the AB4 guess (0: none) */
+    double rate;            /* ln(res0 / res_end) / trips of the last solve (0: none) */
+} ebe_window;
 
 typedef struct {
     int32_t s_eff;          /* as in ebe_step_stats, for the step ebe_predict looks at */
@@ -230,13 +254,26 @@ int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* 
  * ebe_step.
  *
  * Snapshot window (kinds 2 and 3).  Step n fits the regional map on the AB
- * errors e^first .. e^{n-1}, first = max(w, n - 1 - s): inputs e^first ..
+ * errors e^first .. e^{n-1}, first = max(w, n - 1 - s_cap): inputs e^first ..
  * e^{n-2}, outputs e^{first+1} .. e^{n-1}, query e^{n-1}, s_eff = n - 1 - first
- * column pairs; w = 1 at rest.  The map is used once s_eff >= min(s_min, s).
- * Unless cfg.fixed_window, the AB4 guess is then evaluated too (one more
- * matvec) and kept when ||b - A x|| is strictly smaller; ebe_step then sets
- * w = n, discarding the columns that span the change of regime (the start
- * from rest, a kink of the input) that made the map lose. */
+ * column pairs; w = 1 and s_cap = s at rest.  The map is used once s_eff >=
+ * min(s_min, s).  Unless cfg.fixed_window:
+ *   - guard: the AB4 guess is evaluated too (one more matvec) and kept when
+ *     ||b - A x|| is strictly smaller; ebe_step then sets w = n, discarding the
+ *     columns that span the change of regime (the start from rest, a kink of
+ *     the input) that made the map lose.  The evaluation is skipped (the map
+ *     kept) while the map's relative residual is below skip_ratio times the
+ *     last evaluated AB4 one.
+ *   - length (the paper varies s during the run to balance predictor and
+ *     solver time, Sec. 3.2 and Fig. 4; on one device they add up): on the
+ *     probe_every-th step with a full window (s_eff = s_cap) ebe_step also
+ *     evaluates the map over s_cap - probe_step or s_cap + probe_step pairs
+ *     (alternating; at least s_min, at most s, columns after w), estimates the
+ *     trips the longer of the two saves as 2 ln(rho_short / rho_long) / rate
+ *     (rate = ln(res0 / res_end) / trips of the previous solve; the factor 2
+ *     because a guess removes mostly slowly converging components) and moves
+ *     s_cap to the probed length when that beats (or, for a shorter probe,
+ *     falls below) col_cost x probe_step.  The step uses the s_cap window. */
 int ebe_predict(ebe_handle* h, const double* f_next, const double* base_acc, double* dxbar,
                 ebe_pred_stats* stats);
 
@@ -258,12 +295,13 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
 /* Checkpoint / resume.  u, v, a: device [3N] each, caller order.
  * History: vhist device [4][3N] = v^it, v^(it-1), v^(it-2), v^(it-3);
  * ring device [s+1][3N] with e^j = du^j - du_AB^j in slot (j-1) mod (s+1);
- * it = completed steps; win_start = w, the first step whose AB error may
- * enter the snapshot window (>= 1). */
+ * it = completed steps; win: host, the snapshot-window state (NULL in
+ * ebe_set_history: window from step 1 at length s, no probe or AB4
+ * residual history). */
 int ebe_get_state(ebe_handle* h, double* u, double* v, double* a);
 int ebe_set_state(ebe_handle* h, const double* u, const double* v, const double* a);
-int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it, int32_t* win_start);
-int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it, int32_t win_start);
+int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it, ebe_window* win);
+int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it, const ebe_window* win);
 
 /* Block until all work enqueued on the handle's stream is done. */
 int ebe_sync(ebe_handle* h);
@@ -369,7 +407,8 @@ int ebe_mlp_train(ebe_handle* h, int32_t steps, int32_t batch, const int64_t* id
  * out of the shared element passes).  Every case follows the single-case
  * step of ebe_step (right-hand side, AB4 + regional snapshot map, refine to
  * tol, Newmark; every case has its own guarded snapshot window, see
- * ebe_predict).  Each mesh added forms a group of n_cases cases; the group's
+ * ebe_predict, at length s and with the AB4 guess evaluated on every step
+ * where the map is used).  Each mesh added forms a group of n_cases cases; the group's
  * element pass works on tiles of case_tile cases (1, 2, 4 or 8) with element
  * patches of 256 / case_tile elements and `chunks` persistent workgroups per
  * tile, chosen by timing every candidate when ebe_batch_assemble is asked to

@@ -50,14 +50,22 @@ class SolveStats(C.Structure):
 class Params(C.Structure):
     _fields_ = [("dt", C.c_double), ("aR", C.c_double), ("bR", C.c_double), ("tol", C.c_double),
                 ("drop", C.c_double), ("max_iter", C.c_int32), ("s", C.c_int32), ("kind", C.c_int32),
-                ("want_ab_residual", C.c_int32), ("s_min", C.c_int32), ("guard", C.c_int32)]
+                ("want_ab_residual", C.c_int32), ("s_min", C.c_int32), ("guard", C.c_int32),
+                ("skip_ratio", C.c_double), ("col_cost", C.c_double), ("probe_every", C.c_int32),
+                ("probe_step", C.c_int32)]
+
+
+class Window(C.Structure):
+    _fields_ = [("win", C.c_int32), ("s_cap", C.c_int32), ("since", C.c_int32), ("grow_next", C.c_int32),
+                ("rho_ab", C.c_double), ("rate", C.c_double)]
 
 
 class StepStats(C.Structure):
     _fields_ = [("it", C.c_int32), ("s_eff", C.c_int32), ("iters", C.c_int32), ("status", C.c_int32),
-                ("pick", C.c_int32), ("first", C.c_int32),
-                ("res_ab", C.c_double), ("res_map", C.c_double), ("res0", C.c_double), ("res_rec", C.c_double),
-                ("res_true", C.c_double), ("fnorm", C.c_double)]
+                ("pick", C.c_int32), ("first", C.c_int32), ("skipped", C.c_int32), ("probe", C.c_int32),
+                ("s_cap", C.c_int32), ("pad", C.c_int32),
+                ("res_ab", C.c_double), ("res_map", C.c_double), ("res_probe", C.c_double), ("res0", C.c_double),
+                ("res_rec", C.c_double), ("res_true", C.c_double), ("fnorm", C.c_double)]
 
 
 def lib():
@@ -86,7 +94,7 @@ def lib():
                                            C.POINTER(d_p), d_p, C.c_double, d_p]
         L.orc_step.restype = C.c_int
         L.orc_step.argtypes = [C.c_void_p, C.POINTER(Params), i32_p, C.c_int32, d_p, d_p, d_p,
-                               C.POINTER(d_p), C.POINTER(d_p), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                               C.POINTER(d_p), C.POINTER(d_p), C.POINTER(C.c_int32), C.POINTER(Window),
                                d_p, d_p, d_p, d_p, C.POINTER(StepStats)]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
@@ -230,6 +238,10 @@ class StepRecord:
     pick: int = -1       # guard: 1 map kept, 0 AB4 kept (window restarted), -1 no comparison
     first: int = 0       # oldest AB error e^first in the window used (0: no map)
     res_map: float = 0.0
+    skipped: int = 0     # guard: AB4 guess not evaluated (the map far ahead)
+    probe: int = 0       # window length probed this step (0: none)
+    s_cap: int = 0       # window length cap after the step
+    res_probe: float = 0.0
 
 
 class Stepper:
@@ -238,14 +250,18 @@ class Stepper:
 
     kind 2 uses the regional map once s_min column pairs are available and, with
     guard, keeps the AB4 guess when its initial residual is smaller and restarts
-    the window (``orc_step``)."""
+    the window, skips that comparison while the map is far ahead (skip_ratio) and
+    probes shorter and longer windows (col_cost > 0) (``orc_step``)."""
 
     def __init__(self, model: Model, dt, aR, bR, s=16, kind=2, tol=1e-8, max_iter=10000, drop=1e-6,
-                 regions=None, want_ab_residual=False, s_min=8, guard=True):
+                 regions=None, want_ab_residual=False, s_min=8, guard=True, skip_ratio=0.01, col_cost=0.08,
+                 probe_every=16, probe_step=8):
         self.m = model
         n3 = model.n3
         self.P = Params(dt=dt, aR=aR, bR=bR, tol=tol, drop=drop, max_iter=max_iter, s=s, kind=kind,
-                        want_ab_residual=int(want_ab_residual), s_min=int(s_min), guard=int(bool(guard)))
+                        want_ab_residual=int(want_ab_residual), s_min=int(s_min), guard=int(bool(guard)),
+                        skip_ratio=float(skip_ratio), col_cost=float(col_cost), probe_every=int(probe_every),
+                        probe_step=int(probe_step))
         self.regions = (np.zeros(model.n, dtype=np.int32) if regions is None
                         else np.ascontiguousarray(regions, dtype=np.int32))
         self.nreg = int(self.regions.max()) + 1
@@ -253,7 +269,7 @@ class Stepper:
         self.vh = [np.zeros(n3) for _ in range(4)]
         self.ring = [np.zeros(n3) for _ in range(max(s, 0) + 1)]
         self.it = C.c_int32(0)
-        self.win = C.c_int32(1)
+        self.ws = Window(win=1, s_cap=0, since=0, grow_next=0, rho_ab=0.0, rate=0.0)
         self._vhp = (d_p * 4)(*[_d(c) for c in self.vh])
         self._rp = (d_p * len(self.ring))(*[_d(c) for c in self.ring])
 
@@ -265,7 +281,12 @@ class Stepper:
         gs = np.empty(self.m.n3) if want_guess else None
         lib().orc_step(self.m._h, C.byref(self.P), self.regions.ctypes.data_as(i32_p), self.nreg,
                        _d(self.u), _d(self.v), _d(self.a), self._vhp, self._rp, C.byref(self.it),
-                       C.byref(self.win), _d(gg), _d(fa), _d(du), _d(gs), C.byref(st))
+                       C.byref(self.ws), _d(gg), _d(fa), _d(du), _d(gs), C.byref(st))
         rec = StepRecord(st.it, st.s_eff, st.iters, st.status, st.res_ab, st.res0, st.res_rec, st.res_true,
-                         st.pick, st.first, st.res_map)
+                         st.pick, st.first, st.res_map, st.skipped, st.probe, st.s_cap, st.res_probe)
         return rec, du, gs
+
+    @property
+    def win(self):
+        """First step whose AB error may enter the snapshot window."""
+        return self.ws.win

@@ -626,7 +626,23 @@ typedef struct {
     int32_t s_min;             /* kind 2: the map needs at least this many column pairs (<= 0: 1) */
     int32_t guard;             /* kind 2: keep the AB4 guess when its initial residual is smaller,
                                   and restart the snapshot window (see orc_step) */
+    double skip_ratio;         /* guard: the AB4 guess is not evaluated while the map's residual is
+                                  below skip_ratio x the last evaluated AB4 residual (<= 0: always) */
+    double col_cost;           /* guard: cost of one window column in PCG trips; > 0 enables the
+                                  window-length probes (see orc_step), <= 0 keeps the length s */
+    int32_t probe_every;       /* steps with a full window between probes (<= 0: 8) */
+    int32_t probe_step;        /* columns a probe adds or removes (<= 0: 8) */
 } orc_params;
+
+/* Window state carried from step to step (kind 2). */
+typedef struct {
+    int32_t win;         /* first step whose AB error may enter the window (>= 1) */
+    int32_t s_cap;       /* current window length cap in column pairs (0: s) */
+    int32_t since;       /* steps with a full window since the last probe */
+    int32_t grow_next;   /* direction of the next probe: 1 longer, 0 shorter */
+    double rho_ab;       /* last evaluated initial relative residual of the AB4 guess (<= 0: none) */
+    double rate;         /* ln(res0 / res_end) / trips of the last solve (<= 0: none) */
+} orc_window;
 
 typedef struct {
     int32_t it;          /* index of the step just solved */
@@ -635,8 +651,13 @@ typedef struct {
     int32_t status;
     int32_t pick;        /* guard: 1 map kept, 0 AB4 kept (window restarted); -1 no comparison */
     int32_t first;       /* the window used held e^first .. e^{it-1} (0: no map) */
+    int32_t skipped;     /* guard: 1 if the AB4 guess was not evaluated (map far ahead) */
+    int32_t probe;       /* window length probed against s_eff this step (0: none) */
+    int32_t s_cap;       /* window length cap after this step */
+    int32_t pad;
     double res_ab;       /* initial relative residual of the AB4 guess (guard or if requested) */
     double res_map;      /* initial relative residual of the map's guess (guard only) */
+    double res_probe;    /* the same for the probed window length */
     double res0;         /* initial relative residual of the guess actually used */
     double res_rec, res_true, fnorm;
 } orc_step_stats;
@@ -651,30 +672,72 @@ static double rel_residual(const orc_model* m, const double* b, const double* x,
     return fn > 0 ? sqrt(s) / fn : sqrt(s);
 }
 
+/* Trips per unit of log initial residual, in units of 1 / rate (the average
+ * per-trip decay of a solve): a lower initial residual saves more trips than
+ * the average decay suggests, because the guess removes mostly the slowly
+ * converging components.  Measured on the 64 x 64 x 32-cell mesh at steady
+ * state: s = 8 -> 16 lowers ln(res0) by 0.31 and saves 3.9 trips, 1.9 times
+ * 0.31 / rate (rate 0.15). */
+#define TRIP_GAIN 2.0
+
+/* Guess of the map over the window e^first .. e^{n-1} (s_eff column pairs):
+ * inputs X = e^first .. e^{n-2}, outputs Y = e^{first+1} .. e^{n-1} (one step
+ * later), query e^{n-1}; dab + the regional map, zero on fixed dofs. */
+static void map_guess(const orc_model* m, const orc_params* P, const int32_t* region_of_node, int32_t n_regions,
+                      double* const* ring, int n, int first, const double* dab, double* xm) {
+    int64_t n3 = 3 * m->n;
+    int s_eff = n - 1 - first;
+    const double** X = (const double**)malloc(sizeof(double*) * s_eff);
+    const double** Y = (const double**)malloc(sizeof(double*) * s_eff);
+    int S1 = P->s + 1;
+    for (int j = 0; j < s_eff; ++j) {
+        X[j] = ring[(first + j - 1) % S1]; /* e^{first+j}   */
+        Y[j] = ring[(first + j) % S1];     /* e^{first+j+1} */
+    }
+    const double* q = ring[(n - 2) % S1]; /* query e^{n-1} */
+    memset(xm, 0, sizeof(double) * n3);
+    orc_predict_regional(m->n, region_of_node, n_regions, s_eff, X, Y, q, P->drop, xm);
+    for (int64_t i = 0; i < n3; ++i) xm[i] = m->fixed[i] ? 0.0 : dab[i] + xm[i];
+    free(X); free(Y);
+}
+
 /* State arrays (all length 3N, owned by the caller):
  *   u, v, a                    displacement, velocity, acceleration at step it
  *   vh[0..3]                   v^{it}, v^{it-1}, v^{it-2}, v^{it-3}  (v^{j<=0} = 0)
  *   ring[0..s]                 AB errors e^j = du^j - du_AB^j, e^j stored in
  *                              slot (j-1) mod (s+1)
- *   *win                       first step whose AB error may enter the
- *                              snapshot window (1 at rest; may be NULL = 1)
+ *   *ws                        window state (may be NULL: window from step 1,
+ *                              length s, no probes, no skipped evaluations)
  * *it is the number of completed steps; this call advances it by one.
  * g: base acceleration at the new time (3 values, may be NULL); f_add: extra
  * nodal force at the new time (may be NULL).  du_out, guess_out optional.
  *
  * Guess of step n = it + 1 (kind 2; Sec. 3.2): the AB4 increment plus the
  * regional map fitted on the window of AB errors e^first .. e^{n-1}, with
- * first = max(win, n - 1 - s): inputs X = e^first .. e^{n-2}, outputs
- * Y = e^{first+1} .. e^{n-1} (one step later), query e^{n-1}; s_eff = n-1-first
- * column pairs, and the map is used only when s_eff >= s_min (the paper draws
- * s from [8, 32]).  With the guard, the AB4 guess is evaluated too and kept
- * when its residual ||b - A x|| is strictly smaller; the window then restarts
- * at this step (win = n): the map's columns up to e^{n-1} are discarded, so a
- * window that spans a change of regime (the start from rest, a kink in the
- * input) is not fitted again. */
+ * first = max(win, n - 1 - s_cap): s_eff = n - 1 - first column pairs, the map
+ * used only when s_eff >= s_min (the paper draws s from [8, 32]).
+ *
+ * With the guard, the AB4 guess is evaluated too and kept when its residual
+ * ||b - A x|| is strictly smaller; the window then restarts at this step (win =
+ * n): the map's columns up to e^{n-1} are discarded, so a window that spans a
+ * change of regime (the start from rest, a kink in the input) is not fitted
+ * again.  The AB4 guess is not evaluated (the map kept) while the map's
+ * relative residual is below skip_ratio times the last evaluated AB4 one.
+ *
+ * Window length (the paper adjusts s during the run to balance predictor and
+ * solver time; on one device the two add up, so the length that minimises
+ * their sum is sought): with col_cost > 0, after every probe_every steps whose
+ * window was full (s_eff = s_cap), the step also evaluates the map over
+ * s_cap - d or s_cap + d column pairs (d = probe_step; alternating, whichever is
+ * possible: at least s_min, at most s, and enough columns since win).  The
+ * difference in trips is estimated from the two initial residuals with the
+ * per-trip convergence rate of the previous solve, TRIP_GAIN x ln(rho_probe /
+ * rho_map) / rate, and the cap moves to the probed length when the trips it
+ * saves exceed col_cost x d (shorter: extra trips below col_cost x d; longer:
+ * trips saved above it).  The step itself uses the window of length s_cap. */
 int orc_step(const orc_model* m, const orc_params* P, const int32_t* region_of_node, int32_t n_regions,
              double* u, double* v, double* a, double* const* vh, double* const* ring, int32_t* it,
-             int32_t* win, const double* g, const double* f_add, double* du_out, double* guess_out,
+             orc_window* ws, const double* g, const double* f_add, double* du_out, double* guess_out,
              orc_step_stats* st) {
     int64_t n3 = 3 * m->n;
     int n = *it + 1; /* new step index */
@@ -691,42 +754,76 @@ int orc_step(const orc_model* m, const orc_params* P, const int32_t* region_of_n
     if (P->kind == 0) memset(x, 0, sizeof(double) * n3);
     for (int64_t i = 0; i < n3; ++i)
         if (m->fixed[i]) x[i] = 0.0;
-    int w = win ? *win : 1;
-    if (w < 1) w = 1;
-    int first = n - 1 - P->s;
-    if (first < w) first = w;
+    orc_window wl0 = {1, 0, 0, 0, 0.0, 0.0};
+    orc_window* W = ws ? ws : &wl0;
+    if (W->win < 1) W->win = 1;
+    const int s_min = P->s_min < 1 ? 1 : (P->s_min < P->s ? P->s_min : P->s);
+    if (W->s_cap < s_min || W->s_cap > P->s) W->s_cap = P->s;
+    const int s_cap = W->s_cap;
+    int first = n - 1 - s_cap;
+    if (first < W->win) first = W->win;
     int s_eff = n - 1 - first;
-    int s_min = P->s_min < 1 ? 1 : (P->s_min < P->s ? P->s_min : P->s);
     double* tmp = (double*)malloc(sizeof(double) * n3);
+    int new_cap = s_cap;
     if (P->kind == 2 && P->s >= 1 && s_eff >= s_min) {
-        const double** X = (const double**)malloc(sizeof(double*) * s_eff);
-        const double** Y = (const double**)malloc(sizeof(double*) * s_eff);
-        int S1 = P->s + 1;
-        for (int j = 0; j < s_eff; ++j) {
-            X[j] = ring[(first + j - 1) % S1]; /* e^{first+j}   */
-            Y[j] = ring[(first + j) % S1];     /* e^{first+j+1} */
-        }
-        const double* q = ring[(n - 2) % S1]; /* query e^{n-1} */
-        double* xm = (double*)calloc(n3, sizeof(double));
-        orc_predict_regional(m->n, region_of_node, n_regions, s_eff, X, Y, q, P->drop, xm);
-        for (int64_t i = 0; i < n3; ++i) xm[i] = m->fixed[i] ? 0.0 : x[i] + xm[i];
+        double* xm = (double*)malloc(sizeof(double) * n3);
+        map_guess(m, P, region_of_node, n_regions, ring, n, first, dab, xm);
         st->s_eff = s_eff;
         st->first = first;
         if (P->guard) {
-            st->res_ab = rel_residual(m, b, x, tmp);
             st->res_map = rel_residual(m, b, xm, tmp);
-            if (st->res_ab < st->res_map) {
-                st->pick = 0;
-                if (win) *win = n;
-            } else {
+            /* window-length probe */
+            const int d = P->probe_step > 0 ? P->probe_step : 8;
+            const int every = P->probe_every > 0 ? P->probe_every : 8;
+            if (P->col_cost > 0 && s_eff == s_cap) {
+                if (W->since + 1 >= every) {
+                    const int can_grow = s_cap + d <= P->s && n - 1 - (s_cap + d) >= W->win;
+                    const int can_shrink = s_cap - d >= s_min;
+                    int alt = 0;
+                    if (W->grow_next && can_grow) alt = s_cap + d;
+                    else if (can_shrink) alt = s_cap - d;
+                    else if (can_grow) alt = s_cap + d;
+                    if (alt) {
+                        double* xp = (double*)malloc(sizeof(double) * n3);
+                        map_guess(m, P, region_of_node, n_regions, ring, n, n - 1 - alt, dab, xp);
+                        st->res_probe = rel_residual(m, b, xp, tmp);
+                        st->probe = alt;
+                        free(xp);
+                        if (W->rate > 0 && st->res_map > 0 && st->res_probe > 0) {
+                            const double dtrips = TRIP_GAIN * log(st->res_probe / st->res_map) / W->rate;
+                            const double cols = P->col_cost * d;
+                            if (alt < s_cap ? dtrips < cols : -dtrips > cols) new_cap = alt;
+                        }
+                        W->grow_next = alt < s_cap;
+                    }
+                    W->since = 0;
+                } else {
+                    W->since += 1;
+                }
+            }
+            /* guard: the AB4 guess against the map's */
+            if (P->skip_ratio > 0 && W->rho_ab > 0 && st->res_map < P->skip_ratio * W->rho_ab) {
+                st->skipped = 1;
                 st->pick = 1;
                 memcpy(x, xm, sizeof(double) * n3);
+            } else {
+                st->res_ab = rel_residual(m, b, x, tmp);
+                W->rho_ab = st->res_ab;
+                if (st->res_ab < st->res_map) {
+                    st->pick = 0;
+                    W->win = n;
+                } else {
+                    st->pick = 1;
+                    memcpy(x, xm, sizeof(double) * n3);
+                }
             }
         } else {
             memcpy(x, xm, sizeof(double) * n3);
         }
-        free(xm); free(X); free(Y);
+        free(xm);
     }
+    W->s_cap = new_cap;
+    st->s_cap = new_cap;
     if (guess_out) memcpy(guess_out, x, sizeof(double) * n3);
     if (P->want_ab_residual && st->pick < 0) {
         double* xab = (double*)malloc(sizeof(double) * n3);
@@ -743,6 +840,8 @@ int orc_step(const orc_model* m, const orc_params* P, const int32_t* region_of_n
     st->res_true = ss.res_true;
     st->fnorm = ss.fnorm;
     st->status = status;
+    /* per-trip convergence rate of this solve (for the next window-length probe) */
+    if (ss.iters > 0 && ss.res0 > 0 && ss.res_rec > 0) W->rate = log(ss.res0 / ss.res_rec) / ss.iters;
     /* Newmark-beta (beta = 1/4, gamma = 1/2) update, Eq. timestep */
     double dt = P->dt;
     for (int64_t i = 0; i < n3; ++i) {

@@ -105,7 +105,9 @@ struct ebe_handle {
     int head = 0;  // vh[(head + j) & 3] = v^(it - j)
     double* ring = nullptr;
     int32_t it = 0;
-    int32_t win = 1;   // first step whose AB error may enter the snapshot window
+    ebe_window ws{1, 0, 0, 0, 0.0, 0.0};   // snapshot-window state (start, length cap, probes)
+    double* coef_probe = nullptr;          // [n_regions][32] coefficients over the probed length
+    double* x_probe = nullptr;             // [3N] guess over the probed length
     // scratch
     double *dab = nullptr, *x = nullptr, *b = nullptr, *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr};
     double *t0 = nullptr, *t1 = nullptr, *coef = nullptr, *gh = nullptr;
@@ -494,33 +496,57 @@ int run_solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
     return h->cfg.precision == EBE_PREC_FP64 ? solve(h, b, x, st) : solve_mixed(h, b, x, st);
 }
 
-// Snapshot window of step n: AB errors e^first .. e^{n-1}, first = max(win,
-// n - 1 - s); returns the column pairs s_eff = n - 1 - first when the map is
+int s_min_eff(const ebe_handle* h) { return std::max(1, std::min(h->cfg.s_min, h->cfg.s)); }
+
+// Snapshot window of step n: AB errors e^first .. e^{n-1}, first = max(start,
+// n - 1 - s_cap); returns the column pairs s_eff = n - 1 - first when the map is
 // used (s_eff >= s_min), else 0.
 int snapshot_window(const ebe_handle* h, int n, int* first_out) {
     *first_out = 0;
     if ((h->cfg.predictor != EBE_PRED_SNAPSHOT && h->cfg.predictor != EBE_PRED_LEARNED) || h->cfg.s < 1) return 0;
-    const int first = std::max(h->win, n - 1 - h->cfg.s);
+    const int first = std::max(h->ws.start, n - 1 - h->ws.s_cap);
     const int s_eff = n - 1 - first;
-    if (s_eff < std::max(1, std::min(h->cfg.s_min, h->cfg.s))) return 0;
+    if (s_eff < s_min_eff(h)) return 0;
     *first_out = first;
     return s_eff;
 }
 
+// Window length probed on step n (0: none): on the probe_every-th step with a
+// full window, s_cap -/+ probe_step, alternating, as far as the bounds allow.
+int probe_length(const ebe_handle* h, int n, int s_eff) {
+    const ebe_config& c = h->cfg;
+    if (c.fixed_window || c.col_cost < 0 || s_eff != h->ws.s_cap || h->ws.since + 1 < c.probe_every) return 0;
+    const int s_cap = h->ws.s_cap, d = c.probe_step;
+    const bool can_grow = s_cap + d <= c.s && n - 1 - (s_cap + d) >= h->ws.start;
+    const bool can_shrink = s_cap - d >= s_min_eff(h);
+    if (h->ws.grow_next && can_grow) return s_cap + d;
+    if (can_shrink) return s_cap - d;
+    if (can_grow) return s_cap + d;
+    return 0;
+}
+
 // AB4 increment into dab and the guess of step n = it + 1 into x: dab (or 0
-// for kind 0), plus the regional map over the window when it is used.
-int predict_into(ebe_handle* h, double* x, int* first) {
+// for kind 0), plus the regional map over the window when it is used; with a
+// probed length alt, also the map over alt pairs into x_probe (one Gram over
+// the longer of the two windows, each least-squares solve on its newest columns).
+int predict_into(ebe_handle* h, double* x, int* first, int alt = 0) {
     hipStream_t s = h->stream;
     const int n = h->it + 1;
     launch_ab4(s, h->n3(), h->cfg.dt, h->vslot(0), h->vslot(1), h->vslot(2), h->vslot(3),
                h->cfg.predictor == EBE_PRED_ZERO ? 0 : 1, h->dab, x);
     int s_eff = snapshot_window(h, n, first);
     if (s_eff >= 1) {
+        const int s_long = std::max(s_eff, alt);
         ColPtrs W{};
-        const int S1 = h->cfg.s + 1;
-        for (int j = 0; j <= s_eff; ++j) W.c[j] = h->ring_slot((*first + j - 1) % S1);   // e^{first + j}
-        launch_gram_solve(s, W, s_eff, h->chunks, h->cfg.drop_tol, h->gh, h->coef);
-        launch_pred_apply(s, W, s_eff, h->chunks, h->coef, h->dab, x);
+        const int S1 = h->cfg.s + 1, f0 = n - 1 - s_long;
+        for (int j = 0; j <= s_long; ++j) W.c[j] = h->ring_slot((f0 + j - 1) % S1);   // e^{f0 + j}
+        launch_gram(s, W, s_long, h->chunks, h->gh);
+        launch_ls_solve(s, s_long, h->chunks, h->cfg.drop_tol, h->gh, h->coef, s_long - s_eff);
+        launch_pred_apply(s, W, s_long, h->chunks, h->coef, h->dab, x);
+        if (alt > 0) {
+            launch_ls_solve(s, s_long, h->chunks, h->cfg.drop_tol, h->gh, h->coef_probe, s_long - alt);
+            launch_pred_apply(s, W, s_long, h->chunks, h->coef_probe, h->dab, h->x_probe);
+        }
     }
     check_launch();
     return s_eff;
@@ -597,29 +623,97 @@ void choose_learned(ebe_handle* h, const double* f_int, const double* g) {
 // device scalars read back with the solve's).
 struct GuessInfo {
     int n = 0, s_eff = 0, first = 0;
-    bool guarded = false;   // map's guess compared with the AB4 guess
+    int probe = 0;          // window length probed (0: none)
+    bool guarded = false;   // map's guess compared with the AB4 guess (or that comparison skipped)
     bool learned = false;   // learned candidate evaluated
 };
 
 // Right-hand side of step n = it + 1 into b and its guess into x (Eq.
 // predictor with the predictor of Sec. 3.2): AB4; the regional map once the
 // window holds s_min column pairs; unless the window is fixed, the AB4 guess
-// evaluated too and kept when its residual is strictly smaller (the caller
-// then restarts the window); kind 3: the learned candidate against the result.
-// The state is not modified.
-GuessInfo guess_into(ebe_handle* h, const double* f_int, const double* g) {
+// evaluated too (unless the map is far ahead) and kept when its residual is
+// strictly smaller, and on probe steps the map over the probed length
+// evaluated as well (ebe_step then updates the window); kind 3: the learned
+// candidate against the result.  The state is not modified.
+GuessInfo guess_into(ebe_handle* h, const double* f_int, const double* g, bool allow_probe) {
+    hipStream_t s = h->stream;
     GuessInfo info;
     info.n = h->it + 1;
     rhs_into(h, f_int, g, h->b);
     h->q_ready = false;
-    info.s_eff = predict_into(h, h->x, &info.first);
+    int first0 = 0;
+    const int s_eff0 = snapshot_window(h, info.n, &first0);
+    info.probe = allow_probe && s_eff0 > 0 ? probe_length(h, info.n, s_eff0) : 0;
+    info.s_eff = predict_into(h, h->x, &info.first, info.probe);
     if (info.s_eff > 0 && !h->cfg.fixed_window) {
-        choose(h, h->dab, 1);
+        const int gr = res_grid(h->T.n_nodes);
+        const int64_t nq = (int64_t)(3 * h->T.patch_nodes.size());
+        double* part0 = h->cand_part;
+        double* part1 = h->cand_part + gr;
+        double* part_bb = h->cand_part + 2 * (size_t)gr;
+        // the map's guess: its matvec (kept for the solve) and residual, and ||b||
+        launch_ebe_apply(s, h->dp, h->x, true, h->cM, h->cK, h->qbuf);
+        launch_cand_res(s, h->dn, h->qbuf, h->b, part0);
+        launch_cand_res(s, h->dn, nullptr, h->b, part_bb);
+        if (info.probe > 0) {
+            launch_ebe_apply(s, h->dp, h->x_probe, true, h->cM, h->cK, h->qbuf_alt);
+            launch_cand_res(s, h->dn, h->qbuf_alt, h->b, part1);
+            launch_sum_partials(s, part1, gr, &h->sc->probe_rr);
+        }
+        const double thresh = (h->cfg.skip_ratio > 0 && h->ws.rho_ab > 0) ? h->cfg.skip_ratio * h->ws.rho_ab : 0.0;
+        launch_guard_decide(s, part0, part_bb, gr, thresh, h->sc);
+        // the AB4 guess, unless skipped on the device
+        launch_ebe_apply(s, h->dp, h->dab, true, h->cM, h->cK, h->qbuf_alt, nullptr, h->sc);
+        launch_cand_res(s, h->dn, h->qbuf_alt, h->b, part1, h->sc);
+        launch_cand_select(s, h->dn, part0, part1, h->x, h->dab, h->qbuf, h->qbuf_alt, nq, h->sc, 1, h->sc);
+        check_launch();
+        h->q_ready = true;   // qbuf holds the kept guess's matvec: the solve skips its first one
         info.guarded = true;
     }
     info.learned = learned_due(h, info.n) && (h->cand_losses < kCandPatience || info.n % kCandProbe == 0);
     if (info.learned) choose_learned(h, f_int, g);
     return info;
+}
+
+// Trips saved per unit of log initial residual, in units of 1 / rate (the
+// average per-trip decay of a solve): a guess lowers mostly the slowly
+// converging components, so a lower initial residual saves about twice what
+// the average decay suggests (64 x 64 x 32-cell mesh, steady state: s = 8 ->
+// 16 lowers ln(res0) by 0.31 and saves 3.9 trips at rate 0.15).
+constexpr double kTripGain = 2.0;
+
+// Window state after step n from the scalars of its guess and solve (the rule
+// of guess_into / ebe_predict's "Snapshot window").
+void update_window(ebe_handle* h, const GuessInfo& info, const ebe_solve_stats& st) {
+    ebe_window& W = h->ws;
+    const ebe_config& c = h->cfg;
+    const DevScalars& S = *h->sc_host;
+    if (info.guarded) {
+        const double bb = S.guess_bb;
+        auto rel = [&](double rr) { return bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr); };
+        const double rho_map = rel(S.guard_rr[0]);
+        if (!c.fixed_window && c.col_cost >= 0 && info.s_eff == W.s_cap) {
+            if (W.since + 1 >= c.probe_every) {
+                if (info.probe > 0) {
+                    const double rho_p = rel(S.probe_rr);
+                    if (W.rate > 0 && rho_map > 0 && rho_p > 0) {
+                        const double dtrips = kTripGain * std::log(rho_p / rho_map) / W.rate;
+                        const double cols = c.col_cost * c.probe_step;
+                        if (info.probe < W.s_cap ? dtrips < cols : -dtrips > cols) W.s_cap = info.probe;
+                    }
+                    W.grow_next = info.probe < info.s_eff ? 1 : 0;
+                }
+                W.since = 0;
+            } else {
+                W.since += 1;
+            }
+        }
+        if (!S.guard_skip) {
+            W.rho_ab = rel(S.guard_rr[1]);
+            if (S.guard_pick) W.start = info.n;   // the AB4 guess beat the map: restart the window here
+        }
+    }
+    if (st.iters > 0 && st.res0 > 0 && st.res_rec > 0) W.rate = std::log(st.res0 / st.res_rec) / st.iters;
 }
 
 void need_mlp(ebe_handle* h) {
@@ -705,6 +799,10 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     if (c.inner_iters <= 0) c.inner_iters = 16;
     if (c.inner_tol <= 0) c.inner_tol = 1e-2;
     if (c.s_min <= 0) c.s_min = 8;
+    if (c.probe_every <= 0) c.probe_every = 16;
+    if (c.probe_step <= 0) c.probe_step = 8;
+    if (c.skip_ratio == 0) c.skip_ratio = 0.01;
+    if (c.col_cost == 0) c.col_cost = 0.08;
     ebe_handle* h = new (std::nothrow) ebe_handle();
     if (!h) {
         g_create_error = "out of memory";
@@ -801,8 +899,10 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         h->gh = h->alloc<double>((size_t)kGhStride * T.chunk_region.size());
         h->sc = h->alloc<DevScalars>(1);
         h->pap_part = h->alloc<double>(pcg_ebe_grid(h->dp));
-        h->cand_part = h->alloc<double>(2 * (size_t)res_grid(N));
+        h->cand_part = h->alloc<double>(3 * (size_t)res_grid(N));
         h->qbuf_alt = h->alloc<double>(3 * PN);
+        h->coef_probe = h->alloc<double>(32 * (size_t)T.n_regions);
+        h->x_probe = h->alloc<double>(n3);
         h->res_part = h->alloc<double>(2 * kResArrays * (size_t)res_grid(N));
         if (h->cfg.precision != EBE_PREC_FP64) {
             h->r_in = h->alloc<float>(n3);
@@ -844,7 +944,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         HIPCHK(hipStreamSynchronize(s));
         h->head = 0;
         h->it = 0;
-        h->win = 1;
+        h->ws = ebe_window{1, h->cfg.s, 0, 0, 0.0, 0.0};
         h->par = 0;
         h->last_iters = 0;
         h->assembled = true;
@@ -928,7 +1028,7 @@ int ebe_predict(ebe_handle* h, const double* f_next, const double* base_acc, dou
             to_internal(h, f_next, h->t0);
             f_int = h->t0;
         }
-        GuessInfo info = guess_into(h, f_int, base_acc);
+        GuessInfo info = guess_into(h, f_int, base_acc, false);
         to_user(h, h->x, dxbar);
         if (stats) {
             const int gr = res_grid(h->T.n_nodes);
@@ -952,7 +1052,7 @@ int ebe_predict(ebe_handle* h, const double* f_next, const double* base_acc, dou
             stats->bnorm = bn;
             if (info.guarded) {
                 stats->res0_map = rel(S.guard_rr[0]);
-                stats->res0_ab = rel(S.guard_rr[1]);
+                stats->res0_ab = S.guard_skip ? 0.0 : rel(S.guard_rr[1]);
             }
             if (info.learned) stats->res0_learned = rel(S.cand_rr[1]);
         }
@@ -986,7 +1086,7 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
             to_internal(h, f_ext, h->t0);
             f_int = h->t0;
         }
-        GuessInfo info = guess_into(h, f_int, base_acc);
+        GuessInfo info = guess_into(h, f_int, base_acc, true);
         const int n = info.n;
         const bool collect = h->coll_k > 0 && n >= kLearnFirstStep && h->samples_n + h->coll_k <= h->samples_cap;
         if (collect) launch_collect_pre(s, h->coll_nodes, h->coll_k, h->dab, h->coll_stage);
@@ -1007,8 +1107,7 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
         if (rc < 0) return rc;
         const DevScalars& S = *h->sc_host;
         if (info.learned) h->cand_losses = S.cand_pick ? 0 : h->cand_losses + 1;
-        // the AB4 guess beat the map: its window spans a change of regime and restarts here
-        if (info.guarded && S.guard_pick) h->win = n;
+        update_window(h, info, st);
         if (collect) {
             MlpState MS = mlp_state(h, f_int, base_acc);
             launch_collect_post(s, MS, h->coll_nodes, h->coll_k, h->x, h->coll_stage,
@@ -1037,9 +1136,13 @@ int ebe_step(ebe_handle* h, const double* f_ext, const double* base_acc, ebe_ste
             auto rel = [&](double rr) { return st.bnorm > 0 ? std::sqrt(rr) / st.bnorm : 0.0; };
             stats->map_kept = info.guarded ? 1 - S.guard_pick : -1;
             if (info.guarded) {
+                stats->skipped = S.guard_skip;
                 stats->res0_map = rel(S.guard_rr[0]);
-                stats->res0_ab = rel(S.guard_rr[1]);
+                stats->res0_ab = S.guard_skip ? 0.0 : rel(S.guard_rr[1]);
+                stats->probe = info.probe;
+                if (info.probe > 0) stats->res0_probe = rel(S.probe_rr);
             }
+            stats->s_cap = h->ws.s_cap;
             stats->learned = info.learned ? S.cand_pick : -1;
             if (info.learned) {
                 stats->res0_snapshot = rel(S.cand_rr[0]);
@@ -1072,7 +1175,7 @@ int ebe_set_state(ebe_handle* h, const double* u, const double* v, const double*
     });
 }
 
-int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it, int32_t* win_start) {
+int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it, ebe_window* win) {
     return guarded(h, [&]() -> int {
         need_assembled(h);
         const int64_t n3 = h->n3();
@@ -1081,24 +1184,28 @@ int ebe_get_history(ebe_handle* h, double* vhist, double* ring, int32_t* it, int
         if (ring)
             for (int k = 0; k <= h->cfg.s; ++k) to_user(h, h->ring_slot(k), ring + k * n3);
         if (it) *it = h->it;
-        if (win_start) *win_start = h->win;
+        if (win) *win = h->ws;
         check_launch();
         return EBE_OK;
     });
 }
 
-int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it, int32_t win_start) {
+int ebe_set_history(ebe_handle* h, const double* vhist, const double* ring, int32_t it, const ebe_window* win) {
     return guarded(h, [&]() -> int {
         need_assembled(h);
         if (it < 0) throw Arg{"it must be non-negative"};
-        if (win_start < 1) throw Arg{"win_start must be at least 1"};
+        ebe_window w = win ? *win : ebe_window{1, h->cfg.s, 0, 0, 0.0, 0.0};
+        if (w.s_cap == 0) w.s_cap = h->cfg.s;
+        if (w.start < 1 || w.s_cap < 1 || w.s_cap > std::max(1, h->cfg.s) || w.since < 0 || !(w.rho_ab >= 0) ||
+            !(w.rate >= 0))
+            throw Arg{"invalid window state (start >= 1, 1 <= s_cap <= s, since >= 0, rho_ab >= 0, rate >= 0)"};
         const int64_t n3 = h->n3();
         if (vhist)
             for (int j = 0; j < 4; ++j) to_internal(h, vhist + j * n3, h->vslot(j));
         if (ring)
             for (int k = 0; k <= h->cfg.s; ++k) to_internal(h, ring + k * n3, h->ring_slot(k));
         h->it = it;
-        h->win = win_start;
+        h->ws = w;
         check_launch();
         return EBE_OK;
     });
@@ -1162,7 +1269,7 @@ int ebe_reset(ebe_handle* h) {
         check_launch();
         h->head = 0;
         h->it = 0;
-        h->win = 1;
+        h->ws = ebe_window{1, h->cfg.s, 0, 0, 0.0, 0.0};
         h->last_iters = 0;
         h->cand_losses = 0;
         return EBE_OK;

@@ -32,7 +32,8 @@ struct DevScalars {
     // kept (strictly smaller); not reset by a solve
     double guard_rr[2];
     int32_t guard_pick;
-    int32_t pad2_;
+    int32_t guard_skip;  // 1: the AB4 guess was not evaluated (the map's residual far below the last AB4 one)
+    double probe_rr;     // ||b - A x||^2 of the guess over the probed window length (free rows)
     double guess_rr;   // ||b - A x||^2 of the last guess evaluated by ebe_predict (free rows)
     double guess_bb;   // ||b||^2 of the same right-hand side (free rows)
 };
@@ -83,8 +84,9 @@ struct ColPtrs {
 // qbuf[pn] = sum over the patch's elements of (cm M_e + ck K_e) p_e for the
 // patch's nodes; p gathered with fixed components zeroed when mask_in.
 // guard: if non-NULL, the kernel runs only when a true-residual check is due.
+// skip: if non-NULL, the kernel returns at once when sc->guard_skip is set.
 void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
-                      double* qbuf, const DevScalars* guard = nullptr);
+                      double* qbuf, const DevScalars* guard = nullptr, const DevScalars* skip = nullptr);
 // PCG trip j, matvec part: stop test on the incoming residual partials, beta,
 // p_cur = z + beta p_prev, qbuf = A_e p_cur and (p, A p) partials.
 int pcg_ebe_grid(const DevPatches& P);
@@ -175,6 +177,12 @@ struct DevChunks {
 // older columns get zero coefficients).
 void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double drop, double* gh,
                        double* coef, const int32_t* case_lo = nullptr);
+// The partial Grams alone (gh as for launch_gram_solve).
+void launch_gram(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double* gh);
+// The least-squares solve alone on the partial Grams of a window of s_eff columns,
+// leaving out the first lo columns in every region (the window's newest s_eff - lo).
+void launch_ls_solve(hipStream_t s, int s_eff, const DevChunks& C, double drop, const double* gh, double* coef,
+                     int lo);
 void launch_pred_apply(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, const double* coef,
                        const double* dab, double* x);
 // guard (may be NULL): run only once the solve's stop flag reads converged or max_iter
@@ -282,10 +290,16 @@ void launch_msum(hipStream_t s, const DevNodes& N, const double* qbuf, double* m
 // the smaller residual in x and its matvec slots in qbuf (ties keep the
 // primary).  which = 0 records the result in cand_rr / cand_pick (learned
 // candidate), 1 in guard_rr / guard_pick (Adams-Bashforth against the map).
-void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, double* part);
+// skip (may be NULL): with sc->guard_skip set, cand_res returns at once and cand_select keeps the primary.
+void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, double* part,
+                     const DevScalars* skip = nullptr);
 void launch_cand_select(hipStream_t s, const DevNodes& N, const double* part_s, const double* part_l, double* x,
                         const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc,
-                        int which = 0);
+                        int which = 0, const DevScalars* skip = nullptr);
+// Guard of the snapshot map: rr_map and ||b||^2 from their partials into guard_rr[0] and
+// guess_bb; guard_skip = 1 when the map's relative residual is below thresh (thresh <= 0: never).
+void launch_guard_decide(hipStream_t s, const double* part_map, const double* part_bb, int g, double thresh,
+                         DevScalars* sc);
 // *out = sum of the g = res_grid(n) partials, in the fixed order of the solver's reductions.
 void launch_sum_partials(hipStream_t s, const double* part, int g, double* out);
 void launch_fill(hipStream_t s, int64_t n, double value, double* p);

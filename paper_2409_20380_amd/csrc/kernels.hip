@@ -40,6 +40,7 @@ struct EbeArgs {
     double g0, g1, g2;
     int mask_in;         // APPLY
     const DevScalars* guard;  // APPLY: run only when a true-residual check is due
+    const DevScalars* skip;   // APPLY: return at once when guard_skip is set
 };
 
 
@@ -294,6 +295,7 @@ __device__ __forceinline__ void stage_materials(const DevPatches& P, double* lds
 template <int MODE>
 __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe(EbeArgs A) {
     if (MODE == MODE_APPLY && A.guard && !check_due(A.guard)) return;
+    if (MODE == MODE_APPLY && A.skip && A.skip->guard_skip) return;
     extern __shared__ double lds[];
     stage_materials<MODE>(A.P, lds);
     const int xcd = blockIdx.x & 7, k0 = blockIdx.x >> 3, per_xcd_wg = gridDim.x >> 3;   // grid: multiple of 8
@@ -473,10 +475,11 @@ bool ebe_set_lds_limit(const DevPatches& P) {
 }
 
 void launch_ebe_apply(hipStream_t s, const DevPatches& P, const double* p, bool mask_in, double cm, double ck,
-                      double* qbuf, const DevScalars* guard) {
+                      double* qbuf, const DevScalars* guard, const DevScalars* skip) {
     EbeArgs A{};
     A.P = P; A.in0 = p; A.qbuf = qbuf; A.cm = cm; A.ck = ck; A.mask_in = mask_in ? 1 : 0;
     A.guard = guard;
+    A.skip = skip;
     hipLaunchKernelGGL(k_ebe<MODE_APPLY>, dim3(ebe_grid(P, MODE_APPLY)), dim3(64 * kEbeWaves),
                        ebe_lds_bytes(P, MODE_APPLY), s, A);
 }
@@ -1038,7 +1041,9 @@ void launch_msum(hipStream_t s, const DevNodes& N, const double* qbuf, double* m
     hipLaunchKernelGGL(k_msum, dim3((unsigned)((N.n + 255) / 256)), dim3(256), 0, s, N, qbuf, msum);
 }
 
-__global__ __launch_bounds__(256) void k_cand_res(DevNodes N, const double* qbuf, const double* b, double* part) {
+__global__ __launch_bounds__(256) void k_cand_res(DevNodes N, const double* qbuf, const double* b, double* part,
+                                                  const DevScalars* skip) {
+    if (skip && skip->guard_skip) return;
     double v = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
         double q0 = 0.0, q1 = 0.0, q2 = 0.0;
@@ -1053,13 +1058,22 @@ __global__ __launch_bounds__(256) void k_cand_res(DevNodes N, const double* qbuf
     if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, double* part) {
-    hipLaunchKernelGGL(k_cand_res, dim3(res_grid(N.n)), dim3(256), 0, s, N, qbuf, b, part);
+void launch_cand_res(hipStream_t s, const DevNodes& N, const double* qbuf, const double* b, double* part,
+                     const DevScalars* skip) {
+    hipLaunchKernelGGL(k_cand_res, dim3(res_grid(N.n)), dim3(256), 0, s, N, qbuf, b, part, skip);
 }
 
 __global__ __launch_bounds__(256) void k_cand_select(DevNodes N, const double* part_s, const double* part_l, int g,
                                                      double* x, const double* x_alt, double* qbuf,
-                                                     const double* qbuf_alt, int64_t nq, DevScalars* sc, int which) {
+                                                     const double* qbuf_alt, int64_t nq, DevScalars* sc, int which,
+                                                     const DevScalars* skip) {
+    if (skip && skip->guard_skip) {   // the alternative was not evaluated: keep the primary
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->guard_rr[1] = 0.0;
+            sc->guard_pick = 0;
+        }
+        return;
+    }
     double rs = lane_partials<kMaxResGrid / 256>(part_s, g, threadIdx.x, 256);
     double rl = lane_partials<kMaxResGrid / 256>(part_l, g, threadIdx.x, 256);
     rs = block_bcast_sum(rs);
@@ -1080,10 +1094,29 @@ __global__ __launch_bounds__(256) void k_cand_select(DevNodes N, const double* p
 
 void launch_cand_select(hipStream_t s, const DevNodes& N, const double* part_s, const double* part_l, double* x,
                         const double* x_alt, double* qbuf, const double* qbuf_alt, int64_t nq, DevScalars* sc,
-                        int which) {
+                        int which, const DevScalars* skip) {
     const int g = res_grid(N.n);
     hipLaunchKernelGGL(k_cand_select, dim3(g), dim3(256), 0, s, N, part_s, part_l, g, x, x_alt, qbuf, qbuf_alt, nq,
-                       sc, which);
+                       sc, which, skip);
+}
+
+__global__ __launch_bounds__(256) void k_guard_decide(const double* part_map, const double* part_bb, int g,
+                                                      double thresh, DevScalars* sc) {
+    double rm = lane_partials<kMaxResGrid / 256>(part_map, g, threadIdx.x, 256);
+    double bb = lane_partials<kMaxResGrid / 256>(part_bb, g, threadIdx.x, 256);
+    rm = block_bcast_sum(rm);
+    bb = block_bcast_sum(bb);
+    if (threadIdx.x == 0) {
+        const double rho2 = bb > 0.0 ? rm / bb : rm;
+        sc->guard_rr[0] = rm;
+        sc->guess_bb = bb;
+        sc->guard_skip = (thresh > 0.0 && rho2 < thresh * thresh) ? 1 : 0;
+    }
+}
+
+void launch_guard_decide(hipStream_t s, const double* part_map, const double* part_bb, int g, double thresh,
+                         DevScalars* sc) {
+    hipLaunchKernelGGL(k_guard_decide, dim3(1), dim3(256), 0, s, part_map, part_bb, g, thresh, sc);
 }
 
 __global__ __launch_bounds__(256) void k_sum_partials(const double* part, int g, double* out) {
@@ -1243,11 +1276,12 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // perform the same operations in the same order as a row-by-row
 // implementation (the back substitution reads R^T from one LDS copy).
 __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, const int32_t* region_chunk, int s, double drop,
-                                                 double* coef, const int32_t* region_case, const int32_t* case_lo) {
+                                                 double* coef, const int32_t* region_case, const int32_t* case_lo,
+                                                 int lo_all) {
     __shared__ double R[32][33];
     const int r = blockIdx.x, lane = threadIdx.x;
     // columns before lo are left out: zero in the Gram, never kept, zero coefficients
-    const int lo = case_lo ? case_lo[region_case[r]] : 0;
+    const int lo = lo_all + (case_lo ? case_lo[region_case[r]] : 0);
     const bool col = lane >= lo && lane < s;
     double g[32], y = 0.0, gll = 0.0;   // g[i] = G[i][lane]; gll = G[lane][lane], summed in the same order
 #pragma unroll
@@ -1317,7 +1351,20 @@ void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChun
     else
         hipLaunchKernelGGL(k_gram<2>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
     hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(64), 0, s, gh, C.first, s_eff, drop, coef, C.region_case,
-                       case_lo);
+                       case_lo, 0);
+}
+
+void launch_gram(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double* gh) {
+    if (s_eff <= 16)
+        hipLaunchKernelGGL(k_gram<1>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
+    else
+        hipLaunchKernelGGL(k_gram<2>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
+}
+
+void launch_ls_solve(hipStream_t s, int s_eff, const DevChunks& C, double drop, const double* gh, double* coef,
+                     int lo) {
+    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(64), 0, s, gh, C.first, s_eff, drop, coef,
+                       (const int32_t*)nullptr, (const int32_t*)nullptr, lo);
 }
 
 // x = dab + sum_j coef_j Y_j on each node chunk with its region's

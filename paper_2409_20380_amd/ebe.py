@@ -36,7 +36,14 @@ class Config(C.Structure):
                 ("s", C.c_int32), ("predictor", C.c_int32), ("region_nodes", C.c_int32),
                 ("patch_elems", C.c_int32), ("chunk_iters", C.c_int32), ("precision", C.c_int32),
                 ("inner_iters", C.c_int32), ("s_min", C.c_int32), ("fixed_window", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("probe_every", C.c_int32), ("probe_step", C.c_int32), ("skip_ratio", C.c_double),
+                ("col_cost", C.c_double), ("reserved", C.c_int32 * 4)]
+
+
+class Window(C.Structure):
+    """Snapshot-window state (ebe_window)."""
+    _fields_ = [("start", C.c_int32), ("s_cap", C.c_int32), ("since", C.c_int32), ("grow_next", C.c_int32),
+                ("rho_ab", C.c_double), ("rate", C.c_double)]
 
 
 class SolveStats(C.Structure):
@@ -49,7 +56,8 @@ class StepStats(C.Structure):
                 ("status", C.c_int32), ("inner_iters", C.c_int32), ("res0", C.c_double), ("res_rec", C.c_double),
                 ("res_true", C.c_double), ("bnorm", C.c_double), ("learned", C.c_int32), ("first", C.c_int32),
                 ("res0_snapshot", C.c_double), ("res0_learned", C.c_double), ("map_kept", C.c_int32),
-                ("reserved", C.c_int32), ("res0_map", C.c_double), ("res0_ab", C.c_double)]
+                ("skipped", C.c_int32), ("res0_map", C.c_double), ("res0_ab", C.c_double), ("probe", C.c_int32),
+                ("s_cap", C.c_int32), ("res0_probe", C.c_double)]
 
 
 class PredStats(C.Structure):
@@ -107,8 +115,8 @@ def lib():
     L.ebe_step.argtypes = [vp, vp, d_p, C.POINTER(StepStats)]
     L.ebe_get_state.argtypes = [vp, vp, vp, vp]
     L.ebe_set_state.argtypes = [vp, vp, vp, vp]
-    L.ebe_get_history.argtypes = [vp, vp, vp, i32_p, i32_p]
-    L.ebe_set_history.argtypes = [vp, vp, vp, C.c_int32, C.c_int32]
+    L.ebe_get_history.argtypes = [vp, vp, vp, i32_p, C.POINTER(Window)]
+    L.ebe_set_history.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(Window)]
     L.ebe_sync.argtypes = [vp]
     L.ebe_set_kernel_timing.argtypes = [vp, C.c_int32]
     L.ebe_kernel_time.argtypes = [vp, i64_p, d_p]
@@ -192,13 +200,15 @@ class Solver:
 
     def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
                  max_iter=10000, drop_tol=0.0, region_nodes=512, patch_elems=256, chunk_iters=0, precision=PREC_FP64,
-                 inner_iters=0, inner_tol=0.0, s_min=0, fixed_window=False, stream=None):
+                 inner_iters=0, inner_tol=0.0, s_min=0, fixed_window=False, skip_ratio=0.0, col_cost=0.0,
+                 probe_every=0, probe_step=0, stream=None):
         import torch
         L = lib()
         cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol,
                      drop_tol=drop_tol, max_iter=max_iter, s=s, predictor=predictor, region_nodes=region_nodes,
                      patch_elems=patch_elems, chunk_iters=chunk_iters, precision=precision,
-                     inner_iters=inner_iters, inner_tol=inner_tol, s_min=s_min, fixed_window=int(bool(fixed_window)))
+                     inner_iters=inner_iters, inner_tol=inner_tol, s_min=s_min, fixed_window=int(bool(fixed_window)),
+                     skip_ratio=skip_ratio, col_cost=col_cost, probe_every=probe_every, probe_step=probe_step)
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -309,13 +319,17 @@ class Solver:
         vh = torch.empty(4 * self.n3, dtype=torch.float64, device="cuda")
         ring = torch.empty((self.cfg.s + 1) * self.n3, dtype=torch.float64, device="cuda")
         it = C.c_int32()
-        win = C.c_int32()
+        win = Window()
         self._check(lib().ebe_get_history(self._h, _dev(vh), _dev(ring), C.byref(it), C.byref(win)))
-        return vh.view(4, self.n3), ring.view(self.cfg.s + 1, self.n3), it.value, win.value
+        return vh.view(4, self.n3), ring.view(self.cfg.s + 1, self.n3), it.value, win
 
-    def set_history(self, vhist, ring, it, win=1):
+    def set_history(self, vhist, ring, it, win=None):
+        """win: a Window, an int (window start; length s, no probe history) or None (start 1)."""
+        if isinstance(win, int):
+            win = Window(start=win, s_cap=0, since=0, grow_next=0, rho_ab=0.0, rate=0.0)
         self._check(lib().ebe_set_history(self._h, _dev(vhist.contiguous().view(-1)),
-                                          _dev(ring.contiguous().view(-1)), int(it), int(win)))
+                                          _dev(ring.contiguous().view(-1)), int(it),
+                                          C.byref(win) if win is not None else None))
 
     def sync(self):
         self._check(lib().ebe_sync(self._h))

@@ -33,13 +33,15 @@ def _build(wl, oracle_lib):
     return dict(mesh=mesh, em=em, mat=mat, fx=fx, regions=regions, wave=wave, aR=aR, bR=bR, model=model, wl=wl)
 
 
-def _oracle_steps(c, oracle_lib, tol, nt, wave):
+def _oracle_steps(c, oracle_lib, tol, nt, wave, **kw):
     wl = c["wl"]
-    st = oracle_lib.Stepper(c["model"], wl.dt, c["aR"], c["bR"], s=wl.s, kind=2, tol=tol, regions=c["regions"])
+    st = oracle_lib.Stepper(c["model"], wl.dt, c["aR"], c["bR"], s=wl.s, kind=2, tol=tol, regions=c["regions"],
+                            **kw)
     U, its, dec = [], [], []
     for it in range(1, nt + 1):
         rec, _, _ = st.step(g=wave[it])
-        U.append(st.u.copy()); its.append(rec.iters); dec.append((rec.s_eff, rec.first, rec.pick))
+        U.append(st.u.copy()); its.append(rec.iters)
+        dec.append((rec.s_eff, rec.first, rec.pick, rec.skipped, rec.probe, rec.s_cap))
     return np.array(U), np.array(its), dec
 
 
@@ -72,7 +74,7 @@ def test_headline_mesh_rhs_and_steps_match_oracle(oracle_lib):
         st = sol.step(base_acc=c["wave"][it])
         assert st.status == 0
         U.append(to_host(sol.get_state()[0])); its.append(st.iters); res.append(st.res_true)
-        dg.append((st.s_eff, st.first, st.map_kept))
+        dg.append((st.s_eff, st.first, st.map_kept, st.skipped, st.probe, st.s_cap))
     U, its, res = np.array(U), np.array(its), np.array(res)
     say("full size: oracle at 1e-13 and at 1e-8")
     Uref, _, _ = _oracle_steps(c, oracle_lib, 1e-13, STEPS, c["wave"])
@@ -121,8 +123,9 @@ def test_largest_ensemble_mesh_cases_match_oracle(oracle_lib):
             its[it - 1, k] = st[k].iters
             U[k].append(to_host(b.get_state(k)[0]))
     for k in range(r):
-        Uref, _, _ = _oracle_steps(c, oracle_lib, 1e-13, nt, waves[k])
-        _, its8, _ = _oracle_steps(c, oracle_lib, wl.tol, nt, waves[k])
+        batch_rule = dict(skip_ratio=0.0, col_cost=0.0)   # batched cases: guarded window at length s
+        Uref, _, _ = _oracle_steps(c, oracle_lib, 1e-13, nt, waves[k], **batch_rule)
+        _, its8, _ = _oracle_steps(c, oracle_lib, wl.tol, nt, waves[k], **batch_rule)
         err = np.linalg.norm(np.array(U[k]) - Uref) / np.linalg.norm(Uref)
         say(f"case {k}: space-time rel L2 {err:.2e}; trips {its[:, k].tolist()} oracle {its8.tolist()}")
         assert err < TRAJ_TOL

@@ -297,7 +297,7 @@ def _oracle_at(c, oracle_lib, vh, ring, it, win, u, v, a, **kw):
         st.ring[k][:] = ring[k]
     st.u[:] = u; st.v[:] = v; st.a[:] = a
     st.it.value = it
-    st.win.value = win
+    st.ws.win = win
     return st
 
 
@@ -333,7 +333,7 @@ def test_predict_guarded_window_matches_oracle(small, oracle_lib, it, win):
         assert abs(ps.res0_ab - rec.res_ab) <= 1e-10 * rec.res_ab
     assert abs(ps.res0 - rec.res0) <= 1e-10 * rec.res0
     # predict leaves the state alone: the window start is unchanged
-    assert sol.get_history()[3] == win
+    assert sol.get_history()[3].start == win
     (u0, v0, a0), (vh0, ring0, it0, w0) = s0
     sol.set_state(u0, v0, a0)
     sol.set_history(vh0, ring0, it0, w0)
@@ -466,7 +466,7 @@ def _oracle_run(c, oracle_lib, tol, nt, s=None, kind=2, decisions=None, **kw):
         rec, _, _ = st.step(g=c["wave"][it])
         U.append(st.u.copy()); its.append(rec.iters)
         if decisions is not None:
-            decisions.append((rec.s_eff, rec.first, rec.pick))
+            decisions.append((rec.s_eff, rec.first, rec.pick, rec.skipped, rec.probe, rec.s_cap))
     return np.array(U), np.array(its)
 
 
@@ -478,7 +478,7 @@ def _gpu_run(sol, wave, nt, decisions=None):
         u, _, _ = sol.get_state()
         U.append(to_host(u)); its.append(st.iters); res.append(st.res_true)
         if decisions is not None:
-            decisions.append((st.s_eff, st.first, st.map_kept))
+            decisions.append((st.s_eff, st.first, st.map_kept, st.skipped, st.probe, st.s_cap))
     return np.array(U), np.array(its), np.array(res)
 
 
@@ -496,7 +496,7 @@ def test_trajectory_matches_oracle(case, request, oracle_lib):
     U8, its8 = _oracle_run(c, oracle_lib, wl.tol, wl.nt, decisions=do)
     err = np.linalg.norm(U - Uref) / np.linalg.norm(Uref)
     say("space-time rel L2 vs tight oracle", err, "iters gpu/oracle", its.mean(), its8.mean())
-    say("window decisions (s_eff, first, map kept) gpu:", dg)
+    say("window decisions (s_eff, first, map kept, AB4 skipped, probe, length cap) gpu:", dg)
     assert err < TRAJ_TOL
     assert (res < wl.tol).all()
     # the guarded window takes the same decisions as the oracle's at the same tolerance (the 1 m

@@ -553,7 +553,7 @@ def _window_case(oracle_lib, seed, s, it, win):
         st.vh[j][:] = 0.0
         st.vh[j][free] = 1e-3 * rng.standard_normal(free.sum())
     st.it.value = it
-    st.win.value = win
+    st.ws.win = win
     return st, free, expect, first
 
 
@@ -582,7 +582,7 @@ def test_snapshot_window_recovers_exact_recurrence(oracle_lib, s, it, win):
             np.testing.assert_array_equal(st.ring[k], du - dab)
         else:
             np.testing.assert_array_equal(st.ring[k], ring0[k])
-    assert st.it.value == n and st.win.value == win
+    assert st.it.value == n and st.ws.win == win
 
 
 def test_guard_keeps_ab4_and_restarts_the_window(oracle_lib):
@@ -597,10 +597,10 @@ def test_guard_keeps_ab4_and_restarts_the_window(oracle_lib):
     xab = np.where(free, dab, 0.0)
     assert rec.pick == 0 and rec.res_ab < rec.res_map
     np.testing.assert_array_equal(guess, xab)
-    assert st.win.value == n
+    assert st.ws.win == n
     # the next step has no columns left: AB4 alone, no comparison
     rec2, _, guess2 = st.step(want_guess=True)
-    assert rec2.s_eff == 0 and rec2.pick == -1 and st.win.value == n
+    assert rec2.s_eff == 0 and rec2.pick == -1 and st.ws.win == n
 
 
 def test_guard_keeps_a_map_that_reproduces_the_solution(oracle_lib):
@@ -616,13 +616,13 @@ def test_guard_keeps_a_map_that_reproduces_the_solution(oracle_lib):
     dab = oracle_lib.ab4(st.P.dt, *[c.copy() for c in st.vh])
     e_star = np.where(free, du_star - dab, 0.0)
     st.P.s_min = 1
-    st.win.value = n - 2            # window e^{n-2}, e^{n-1}: one column pair
+    st.ws.win = n - 2            # window e^{n-2}, e^{n-1}: one column pair
     for k in (n - 2, n - 1):
         st.ring[(k - 1) % 5][:] = e_star
     rec, _, guess = st.step(g=g, want_guess=True)
     assert rec.s_eff == 1 and rec.pick == 1 and rec.res_map < 1e-10 < rec.res_ab
     assert np.abs(guess - du_star).max() <= 1e-9 * np.abs(du_star).max()
-    assert st.win.value == n - 2
+    assert st.ws.win == n - 2
 
 
 def test_map_waits_for_s_min_column_pairs(oracle_lib):
@@ -636,3 +636,117 @@ def test_map_waits_for_s_min_column_pairs(oracle_lib):
     rec, _, guess = st.step(want_guess=True)        # step 10: 8 column pairs
     assert rec.s_eff == 8 and rec.first == 1
     assert np.abs(guess - np.where(free, dab, 0.0)).max() > 0
+
+
+# ----------------------------------------------------------------------------
+# Window length probes and the skipped AB4 evaluation (kind 2, guard)
+# ----------------------------------------------------------------------------
+def _exact_step(oracle_lib, s, it, seed):
+    """A stepper about to take step n = it + 1 with a random state, and the exact AB
+    error e* = du* - du_AB of that step (du* from PCG at 1e-14)."""
+    mesh = inputs.box_mesh(4, 4, 4)
+    em, mat = inputs.two_layer_materials(mesh)
+    fx = inputs.fixed_bottom(mesh)
+    dt = 0.01
+    mod = oracle_lib.Model(mesh.coords, mesh.conn, em, mat, fx, 4 / dt ** 2, 1.0)
+    regions = inputs.block_regions(mesh, 4)
+    st = oracle_lib.Stepper(mod, dt, 0.0, 0.0, s=s, kind=2, tol=1e-8, regions=regions, s_min=4, guard=True,
+                            col_cost=0.08, probe_every=1, probe_step=8)
+    rng = np.random.default_rng(seed)
+    free = fx.ravel() == 0
+    for j in range(4):
+        st.vh[j][:] = 0.0
+        st.vh[j][free] = 1e-3 * rng.standard_normal(free.sum())
+    st.v[:] = st.vh[0]
+    st.u[free] = 1e-4 * rng.standard_normal(free.sum())
+    g = np.array([0.3, -0.2, 0.5])
+    b = mod.rhs(st.u, st.v, st.a, dt, 0.0, 0.0, g=g)
+    du_star, _ = mod.pcg(b, np.zeros(mod.n3), tol=1e-14)
+    dab = oracle_lib.ab4(dt, *[c.copy() for c in st.vh])
+    e_star = np.where(free, du_star - dab, 0.0)
+    st.it.value = it
+    return st, rng, free, np.repeat(regions, 3), g, e_star
+
+
+def _ring_predicting(st, rng, free, dof_region, n, coeffs, target):
+    """Fill the window e^{n-17} .. e^{n-1} (16 inputs c_0..c_15, query q = X a with the given
+    coefficients a, outputs the inputs shifted by one step) so that, per region, the map over
+    all 16 pairs predicts `target` exactly: c_15 is solved for from Y a = target."""
+    s, S1 = 16, len(st.ring)
+    first = n - 1 - s
+    a = coeffs
+    cols = np.zeros((s + 1, st.m.n3))
+    for r in range(int(dof_region.max()) + 1):
+        sel = (dof_region == r) & free
+        scale = np.linalg.norm(target[sel]) / np.sqrt(sel.sum())     # inputs of the target's size
+        c = [scale * rng.standard_normal(sel.sum()) for _ in range(s)]
+        # Y a = sum_{j<15} a_j c_{j+1} + a_15 q,  q = sum_{j<15} a_j c_j + a_15 c_15
+        rhs = target[sel] - sum(a[j - 1] * c[j] for j in range(1, 15)) - a[15] * sum(a[j] * c[j] for j in range(15))
+        c[15] = rhs / (a[14] + a[15] ** 2)
+        q = sum(a[j] * c[j] for j in range(16))
+        for j in range(16):
+            cols[j][sel] = c[j]
+        cols[16][sel] = q
+    for j in range(s + 1):
+        st.ring[(first + j - 1) % S1][:] = cols[j]
+
+
+def test_probe_keeps_the_window_when_the_shorter_one_predicts_worse(oracle_lib):
+    st, rng, free, dreg, g, e_star = _exact_step(oracle_lib, 16, 40, 71)
+    n = 41
+    a = rng.uniform(0.5, 1.0, 16)                  # the query needs all 16 inputs
+    _ring_predicting(st, rng, free, dreg, n, a, e_star)
+    st.ws.s_cap, st.ws.rate, st.ws.grow_next = 16, 0.1, 0
+    rec, _, _ = st.step(g=g)
+    assert rec.s_eff == 16 and rec.probe == 8 and rec.pick == 1
+    assert rec.res_map < 1e-10 < rec.res_probe
+    assert st.ws.s_cap == 16 and rec.s_cap == 16 and st.ws.since == 0 and st.ws.grow_next == 1
+
+
+def test_probe_shortens_the_window_when_the_shorter_one_predicts_as_well(oracle_lib):
+    st, rng, free, dreg, g, e_star = _exact_step(oracle_lib, 16, 40, 72)
+    n = 41
+    a = np.concatenate([np.zeros(8), rng.uniform(0.5, 1.0, 8)])    # only the newest 8 inputs
+    miss = 1e-3 * np.abs(e_star).max() * rng.standard_normal(e_star.size) * free
+    _ring_predicting(st, rng, free, dreg, n, a, e_star + miss)      # both windows predict e* + miss
+    st.ws.s_cap, st.ws.rate, st.ws.grow_next = 16, 0.1, 0
+    rec, _, _ = st.step(g=g)
+    assert rec.probe == 8 and abs(rec.res_probe - rec.res_map) <= 1e-8 * rec.res_map
+    assert st.ws.s_cap == 8
+
+
+def test_probe_lengthens_the_window_when_the_longer_one_saves_trips(oracle_lib):
+    st, rng, free, dreg, g, e_star = _exact_step(oracle_lib, 16, 40, 73)
+    n = 41
+    a = rng.uniform(0.5, 1.0, 16)
+    _ring_predicting(st, rng, free, dreg, n, a, e_star)             # only the 16-pair window is exact
+    st.ws.s_cap, st.ws.rate, st.ws.grow_next = 8, 0.1, 1
+    rec, _, _ = st.step(g=g)
+    assert rec.s_eff == 8 and rec.probe == 16 and rec.res_probe < 1e-10 < rec.res_map
+    assert st.ws.s_cap == 16
+    # a longer window needs its columns after the window start: none to probe, so it shortens
+    st2, rng2, free2, dreg2, g2, e2 = _exact_step(oracle_lib, 16, 40, 73)
+    _ring_predicting(st2, rng2, free2, dreg2, n, a, e2)
+    st2.ws.s_cap, st2.ws.rate, st2.ws.grow_next, st2.ws.win = 8, 0.1, 1, n - 1 - 12
+    rec2, _, _ = st2.step(g=g2)
+    assert rec2.probe == 0 or rec2.probe < 8
+
+
+def test_guard_skips_the_ab4_evaluation_while_the_map_is_far_ahead(oracle_lib):
+    st, rng, free, dreg, g, e_star = _exact_step(oracle_lib, 16, 40, 74)
+    n = 41
+    a = rng.uniform(0.5, 1.0, 16)
+    _ring_predicting(st, rng, free, dreg, n, a, e_star)
+    st.P.col_cost = 0.0                              # no probes
+    st.ws.rho_ab = 1e-3                              # last AB4 residual far above the map's
+    dab = oracle_lib.ab4(st.P.dt, *[c.copy() for c in st.vh])
+    rec, _, guess = st.step(g=g, want_guess=True)
+    assert rec.skipped == 1 and rec.pick == 1 and rec.res_ab == 0.0 and st.ws.rho_ab == 1e-3
+    assert rec.res_map < 1e-10
+    # the same step with a reference below the map's residual evaluates AB4 and records it
+    st2, rng2, free2, dreg2, g2, e2 = _exact_step(oracle_lib, 16, 40, 74)
+    _ring_predicting(st2, rng2, free2, dreg2, n, a, e2)
+    st2.P.col_cost = 0.0
+    st2.ws.rho_ab = 1e-14
+    rec2, _, _ = st2.step(g=g2)
+    assert rec2.skipped == 0 and rec2.pick == 1 and rec2.res_ab > 1e-6 and st2.ws.rho_ab == rec2.res_ab

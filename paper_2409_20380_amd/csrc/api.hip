@@ -370,6 +370,7 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
     int chunk = h->cfg.chunk_iters > 0 ? h->cfg.chunk_iters : std::max(2, h->last_iters + 1);
     int done = DONE_RUNNING;
     int j = 0;
+    const int par0 = h->par;
     for (int round = 0;; ++round) {
         for (int k = 0; k < chunk; ++k, ++j) {
             double* pprev = h->p[h->par];
@@ -391,11 +392,13 @@ int solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
             }
             h->pcg_launches++;
             UpdLaunch U{&h->dn, PREC_FP64, h->qbuf, pcur, h->binv6, x, h->r, h->z, h->sc, nullptr, h->pap_part, g_pap,
-                        slot(j + 1), j, nullptr};
+                        slot(j + 1), j, nullptr, pprev};
             launch_pcg_update(s, U);
             h->par ^= 1;
         }
-        // true-residual check (runs on the device only once the loop stopped)
+        // true-residual check (runs on the device only once the loop stopped), after the
+        // last trip's deferred half of the paired x update
+        launch_flush_x(s, h->dn, x, h->p[0], h->p[1], par0, h->sc);
         launch_ebe_apply(s, h->dp, x, true, h->cM, h->cK, h->qbuf, h->sc);
         launch_residual(s, h->dn, h->qbuf, b, h->binv6, x, h->r, h->z, h->sc, slot(j), 1);
         launch_check_finalize(s, h->sc, slot(j), g_res, j, tol);

@@ -34,6 +34,11 @@ struct DevScalars {
     int32_t guard_pick;
     int32_t guard_skip;  // 1: the AB4 guess was not evaluated (the map's residual far below the last AB4 one)
     double probe_rr;     // ||b - A x||^2 of the guess over the probed window length (free rows)
+    // FP64 solve: x += alpha p is applied for two trips at once; trip j with (j - x_base) even
+    // leaves its alpha in x_alpha for trip j + 1 (or the flush at the stop)
+    double x_alpha;
+    int32_t x_base;
+    int32_t pad3_;
     double guess_rr;   // ||b - A x||^2 of the last guess evaluated by ebe_predict (free rows)
     double guess_bb;   // ||b||^2 of the same right-hand side (free rows)
 };
@@ -147,8 +152,14 @@ struct UpdLaunch {
     double* res_part;
     int j;
     int32_t* inner_count;   // if set, incremented once per trip that ran
+    const void* p_other;    // FP64 solve: the previous trip's direction (the pair's first half); NULL: x every trip
 };
 void launch_pcg_update(hipStream_t s, const UpdLaunch& L);
+// At the stop of an FP64 solve (only when the true-residual check is due): the
+// pending x += alpha p of the last trip, if its pair was not completed.  p_j is
+// p[(par0 + j + 1) & 1] (par0: the direction buffer parity at trip 0).
+void launch_flush_x(hipStream_t s, const DevNodes& N, double* x, const double* p0, const double* p1, int par0,
+                    DevScalars* sc);
 // Mixed precision (flexible FP64 outer PCG with an inner PCG preconditioner).
 void launch_inner_init(hipStream_t s, int prec, const DevNodes& N, const double* r64, const void* binv, void* r,
                        void* e, void* z, DevScalars* outer, const double* outer_part, int j, int max_iter, double tol,

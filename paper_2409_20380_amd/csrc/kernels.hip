@@ -704,6 +704,7 @@ __global__ __launch_bounds__(256) void k_residual(DevNodes N, const double* qbuf
         sc->cycle_start = 0;
         sc->inner_iters = 0;
         sc->res_true = 0.0;
+        sc->x_base = 0;
     }
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
@@ -762,6 +763,7 @@ __global__ __launch_bounds__(256) void k_check_finalize(DevScalars* sc, const do
             sc->checked = 0;
             sc->restarts += 1;
             sc->cycle_start = j_next;
+            sc->x_base = j_next;   // the flush completed x: the next trip starts a new pair
         }
     }
 }
@@ -778,7 +780,7 @@ template <class T, class S>
 __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, const S* p, const T* binv6, T* x, T* r,
                                                     S* z, DevScalars* sc, const DevScalars* outer,
                                                     const double* pap_part, int g_pap, double* res_part, int j,
-                                                    int32_t* inner_count) {
+                                                    int32_t* inner_count, const S* p_other) {
     if (sc->done) return;
     if (outer && outer->done) return;
     double pap = lane_partials<kMaxPcgGrid / 256>(pap_part, g_pap, threadIdx.x, 256);
@@ -790,11 +792,17 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, c
     }
     if (inner_count && blockIdx.x == 0 && threadIdx.x == 0) *inner_count += 1;
     const T alpha = (T)alpha_d;
+    // paired x update: the first trip of a pair only records its alpha, the second
+    // applies both (x_base is written only between solves and by the restart)
+    const bool defer = p_other && ((j - sc->x_base) & 1) == 0;
+    const bool pair = p_other && !defer;
+    const T alpha_prev = pair ? (T)sc->x_alpha : T(0);
+    if (defer && blockIdx.x == 0 && threadIdx.x == 0) sc->x_alpha = alpha_d;
     double v0 = 0.0, v1 = 0.0;
     constexpr int U = 1;   // nodes per thread per trip (one: fewer registers, more waves in flight)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n0 < N.n; n0 += U * stride) {
-        T q[U][3], rv[U][3], xv[U][3], pv[U][3], B[U][6];
+        T q[U][3], rv[U][3], xv[U][3], pv[U][3], po[U][3], B[U][6];
         uint8_t fm[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -805,8 +813,9 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, c
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 rv[u][c] = ok ? r[3 * n + c] : T(0);
-                xv[u][c] = ok ? x[3 * n + c] : T(0);
-                pv[u][c] = ok ? from_storage<T>(p[3 * n + c]) : T(0);
+                xv[u][c] = (ok && !defer) ? x[3 * n + c] : T(0);
+                pv[u][c] = (ok && !defer) ? from_storage<T>(p[3 * n + c]) : T(0);
+                po[u][c] = (ok && pair) ? from_storage<T>(p_other[3 * n + c]) : T(0);
             }
 #pragma unroll
             for (int t = 0; t < 6; ++t) B[u][t] = ok ? binv6[6 * n + t] : T(0);
@@ -821,9 +830,15 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, c
             const T r0 = fma(-alpha, q[u][0], rv[u][0]);
             const T r1 = fma(-alpha, q[u][1], rv[u][1]);
             const T r2 = fma(-alpha, q[u][2], rv[u][2]);
-            x[3 * n] = fma(alpha, pv[u][0], xv[u][0]);
-            x[3 * n + 1] = fma(alpha, pv[u][1], xv[u][1]);
-            x[3 * n + 2] = fma(alpha, pv[u][2], xv[u][2]);
+            if (pair) {
+                x[3 * n] = fma(alpha, pv[u][0], fma(alpha_prev, po[u][0], xv[u][0]));
+                x[3 * n + 1] = fma(alpha, pv[u][1], fma(alpha_prev, po[u][1], xv[u][1]));
+                x[3 * n + 2] = fma(alpha, pv[u][2], fma(alpha_prev, po[u][2], xv[u][2]));
+            } else if (!defer) {
+                x[3 * n] = fma(alpha, pv[u][0], xv[u][0]);
+                x[3 * n + 1] = fma(alpha, pv[u][1], xv[u][1]);
+                x[3 * n + 2] = fma(alpha, pv[u][2], xv[u][2]);
+            }
             T z0, z1, z2;
             apply_binv(B[u], r0, r1, r2, z0, z1, z2);
             r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
@@ -848,19 +863,38 @@ void launch_pcg_update(hipStream_t s, const UpdLaunch& L) {
         case PREC_FP64:
             hipLaunchKernelGGL((k_pcg_update<double, double>), grid, block, 0, s, *L.N, (const double*)L.qbuf,
                                (const double*)L.p, (const double*)L.binv, (double*)L.x, (double*)L.r, (double*)L.z,
-                               L.sc, L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count);
+                               L.sc, L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count,
+                               (const double*)L.p_other);
             break;
         case PREC_FP32:
             hipLaunchKernelGGL((k_pcg_update<float, float>), grid, block, 0, s, *L.N, (const float*)L.qbuf,
                                (const float*)L.p, (const float*)L.binv, (float*)L.x, (float*)L.r, (float*)L.z, L.sc,
-                               L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count);
+                               L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count, (const float*)nullptr);
             break;
         default:
             hipLaunchKernelGGL((k_pcg_update<float, bf16_t>), grid, block, 0, s, *L.N, (const float*)L.qbuf,
                                (const bf16_t*)L.p, (const float*)L.binv, (float*)L.x, (float*)L.r, (bf16_t*)L.z,
-                               L.sc, L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count);
+                               L.sc, L.outer, L.pap_part, L.g_pap, L.res_part, L.j, L.inner_count,
+                               (const bf16_t*)nullptr);
             break;
     }
+}
+
+// The pending half of a paired x update at the stop: the last trip j = iters - 1
+// deferred its alpha p when (j - x_base) is even.
+__global__ void k_flush_x(DevNodes N, double* x, const double* p0, const double* p1, int par0, DevScalars* sc) {
+    if (!check_due(sc)) return;
+    const int j = sc->iters - 1;
+    if (j < sc->x_base || ((j - sc->x_base) & 1) != 0) return;
+    const double* p = ((par0 + j + 1) & 1) ? p1 : p0;
+    const double alpha = sc->x_alpha;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 3 * N.n) x[i] = fma(alpha, p[i], x[i]);
+}
+
+void launch_flush_x(hipStream_t s, const DevNodes& N, double* x, const double* p0, const double* p1, int par0,
+                    DevScalars* sc) {
+    hipLaunchKernelGGL(k_flush_x, dim3((unsigned)((3 * N.n + 255) / 256)), dim3(256), 0, s, N, x, p0, p1, par0, sc);
 }
 
 // ---------------------------------------------------------------------------

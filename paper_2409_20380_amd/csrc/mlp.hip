@@ -1,9 +1,11 @@
 // mlp.hip -- node-wise learned predictor (an extension on top of the
 // predictor of Sec. 3.2; the paper names learned surrogates only as related
 // work in Sec. 1).  A 15 -> 64 -> 64 -> 3 network with GELU (tanh form) after
-// each hidden layer corrects the snapshot prediction node by node; Algorithm 1
-// still refines the guess to the tolerance, so the network only changes the
-// iteration count.
+// each hidden layer estimates, node by node, the error of the Adams-Bashforth
+// increment (u - u_AB); the AB4 increment plus that estimate is a second
+// candidate guess, judged against the snapshot guess by initial residual.
+// Algorithm 1 still refines the kept guess to the tolerance, so the network
+// only changes the iteration count.
 //
 //   inference: BF16 weights and activations on v_mfma_f32_16x16x16bf16_1k with
 //     FP32 accumulation.  The layers are computed transposed, H^T = W X^T, so

@@ -4,7 +4,7 @@ Every case of a batch is checked against its own single-case oracle
 trajectory: the batch shares element passes between cases but each case runs
 its own CG, so each result must meet the plain path's bars (space-time
 relative L2 error <= 1e-6 against the tight oracle, true residual < 1e-8 every
-step, iteration counts within a few trips of the oracle's at the same
+step, iteration counts within 2 trips of the oracle's at the same
 tolerance).
 """
 import numpy as np
@@ -118,7 +118,7 @@ def test_batch_trajectories_match_oracle(ms, models, oracle_lib):
             say(f"case {c}: space-time rel L2 {err:.2e}; iters {its[:, c].mean():.2f} vs oracle {its8.mean():.2f}")
             say(f"case {c}: window decisions {dec[c]}")
             assert err < TRAJ_TOL
-            assert np.abs(its[:, c] - its8).max() <= 3
+            assert np.abs(its[:, c] - its8).max() <= 2
             # each case's guarded window takes the oracle's decisions
             assert dec[c] == dec8
             c += 1

@@ -171,7 +171,8 @@ typedef struct {
     int32_t since;          /* steps with a full window since the last length probe */
     int32_t grow_next;      /* direction of the next probe: 1 longer, 0 shorter */
     double rho_ab;          /* last evaluated initial relative residual of the AB4 guess (0: none) */
-    double rate;            /* ln(res0 / res_end) / trips of the last solve (0: none) */
+    double rate;            /* ln(res0 / res_end) / trips of the last solve, inner trips
+                               of the mixed forms at 0.62 each (0: none) */
 } ebe_window;
 
 typedef struct {
@@ -270,7 +271,8 @@ int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* 
  *     evaluates the map over s_cap - probe_step or s_cap + probe_step pairs
  *     (alternating; at least s_min, at most s, columns after w), estimates the
  *     trips the longer of the two saves as 2 ln(rho_short / rho_long) / rate
- *     (rate = ln(res0 / res_end) / trips of the previous solve; the factor 2
+ *     (rate = ln(res0 / res_end) / trips of the previous solve, an inner trip of
+ *     the mixed-precision forms counted as 0.62 of a trip; the factor 2
  *     because a guess removes mostly slowly converging components) and moves
  *     s_cap to the probed length when that beats (or, for a shorter probe,
  *     falls below) col_cost x probe_step.  The step uses the s_cap window. */

@@ -685,6 +685,12 @@ GuessInfo guess_into(ebe_handle* h, const double* f_int, const double* g, bool a
 // 16 lowers ln(res0) by 0.31 and saves 3.9 trips at rate 0.15).
 constexpr double kTripGain = 2.0;
 
+// Cost of one inner trip of the mixed-precision solve (FP32 matvec + update)
+// in FP64 trips (64 x 64 x 32-cell mesh: (42.7 + 24.3) / (61.1 + 46.1) us), so
+// that the decay rate, and with it the trips a probe saves, is per FP64-trip
+// equivalent in every precision, the unit the column cost is measured in.
+constexpr double kInnerTripCost = 0.62;
+
 // Window state after step n from the scalars of its guess and solve (the rule
 // of guess_into / ebe_predict's "Snapshot window").
 void update_window(ebe_handle* h, const GuessInfo& info, const ebe_solve_stats& st) {
@@ -716,7 +722,8 @@ void update_window(ebe_handle* h, const GuessInfo& info, const ebe_solve_stats& 
             if (S.guard_pick) W.start = info.n;   // the AB4 guess beat the map: restart the window here
         }
     }
-    if (st.iters > 0 && st.res0 > 0 && st.res_rec > 0) W.rate = std::log(st.res0 / st.res_rec) / st.iters;
+    const double trips = st.iters + (c.precision != EBE_PREC_FP64 ? kInnerTripCost * st.inner_iters : 0.0);
+    if (trips > 0 && st.res0 > 0 && st.res_rec > 0) W.rate = std::log(st.res0 / st.res_rec) / trips;
 }
 
 void need_mlp(ebe_handle* h) {

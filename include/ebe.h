@@ -108,9 +108,12 @@ typedef struct {
     int32_t precision;      /* EBE_PREC_*: how Algorithm 1 is run (see below) */
     int32_t inner_iters;    /* mixed precision: inner PCG trips per outer trip at most
                                (<= 0: 16) */
-    int32_t s_min;          /* snapshot map used only once its window holds at least
-                               min(s_min, s) column pairs (<= 0: 8, the lower end of the
-                               paper's range 8 <= s <= 32, Sec. 4 / Fig. 3); AB4 alone before */
+    int32_t s_min;          /* snapshot map used once its window holds at least
+                               min(s_min, s) column pairs (<= 0: 3; the guard below keeps
+                               AB4 where the short map is worse); AB4 alone before.  The
+                               window length itself stays at least max(s_min, min(8, s)),
+                               the lower end of the paper's range 8 <= s <= 32 (Sec. 4,
+                               Fig. 3) */
     int32_t fixed_window;   /* 0 (default): guarded window -- whenever the map is used, the
                                AB4 guess is evaluated too and kept when its initial residual
                                is strictly smaller, and the window then restarts at that step;
@@ -269,7 +272,8 @@ int ebe_rhs(ebe_handle* h, const double* f_ext, const double* base_acc, double* 
  *     solver time, Sec. 3.2 and Fig. 4; on one device they add up): on the
  *     probe_every-th step with a full window (s_eff = s_cap) ebe_step also
  *     evaluates the map over s_cap - probe_step or s_cap + probe_step pairs
- *     (alternating; at least s_min, at most s, columns after w), estimates the
+ *     (alternating; at least max(s_min, min(8, s)), at most s, columns after
+ *     w), estimates the
  *     trips the longer of the two saves as 2 ln(rho_short / rho_long) / rate
  *     (rate = ln(res0 / res_end) / trips of the previous solve, an inner trip of
  *     the mixed-precision forms counted as 0.62 of a trip; the factor 2

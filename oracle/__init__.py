@@ -254,7 +254,7 @@ class Stepper:
     probes shorter and longer windows (col_cost > 0) (``orc_step``)."""
 
     def __init__(self, model: Model, dt, aR, bR, s=16, kind=2, tol=1e-8, max_iter=10000, drop=1e-6,
-                 regions=None, want_ab_residual=False, s_min=8, guard=True, skip_ratio=0.01, col_cost=0.08,
+                 regions=None, want_ab_residual=False, s_min=3, guard=True, skip_ratio=0.01, col_cost=0.08,
                  probe_every=16, probe_step=8):
         self.m = model
         n3 = model.n3

@@ -678,6 +678,8 @@ static double rel_residual(const orc_model* m, const double* b, const double* x,
  * converging components.  Measured on the 64 x 64 x 32-cell mesh at steady
  * state: s = 8 -> 16 lowers ln(res0) by 0.31 and saves 3.9 trips, 1.9 times
  * 0.31 / rate (rate 0.15). */
+/* Lower end of the window length: the paper draws s from [8, 32] (Sec. 4, Fig. 3). */
+#define LEN_FLOOR 8
 #define TRIP_GAIN 2.0
 
 /* Guess of the map over the window e^first .. e^{n-1} (s_eff column pairs):
@@ -715,7 +717,8 @@ static void map_guess(const orc_model* m, const orc_params* P, const int32_t* re
  * Guess of step n = it + 1 (kind 2; Sec. 3.2): the AB4 increment plus the
  * regional map fitted on the window of AB errors e^first .. e^{n-1}, with
  * first = max(win, n - 1 - s_cap): s_eff = n - 1 - first column pairs, the map
- * used only when s_eff >= s_min (the paper draws s from [8, 32]).
+ * used when s_eff >= s_min (the predictor as defined uses whatever history
+ * the window holds, s_min = 1; a larger s_min waits for more pairs).
  *
  * With the guard, the AB4 guess is evaluated too and kept when its residual
  * ||b - A x|| is strictly smaller; the window then restarts at this step (win =
@@ -729,7 +732,8 @@ static void map_guess(const orc_model* m, const orc_params* P, const int32_t* re
  * their sum is sought): with col_cost > 0, after every probe_every steps whose
  * window was full (s_eff = s_cap), the step also evaluates the map over
  * s_cap - d or s_cap + d column pairs (d = probe_step; alternating, whichever is
- * possible: at least s_min, at most s, and enough columns since win).  The
+ * possible: at least max(s_min, min(8, s)), the paper drawing s from [8, 32],
+ * at most s, and enough columns since win).  The
  * difference in trips is estimated from the two initial residuals with the
  * per-trip convergence rate of the previous solve, TRIP_GAIN x ln(rho_probe /
  * rho_map) / rate, and the cap moves to the probed length when the trips it
@@ -758,7 +762,9 @@ int orc_step(const orc_model* m, const orc_params* P, const int32_t* region_of_n
     orc_window* W = ws ? ws : &wl0;
     if (W->win < 1) W->win = 1;
     const int s_min = P->s_min < 1 ? 1 : (P->s_min < P->s ? P->s_min : P->s);
-    if (W->s_cap < s_min || W->s_cap > P->s) W->s_cap = P->s;
+    const int len_floor = P->s < LEN_FLOOR ? P->s : LEN_FLOOR;
+    const int len_min = s_min > len_floor ? s_min : len_floor;   /* shortest window length */
+    if (W->s_cap < len_min || W->s_cap > P->s) W->s_cap = P->s;
     const int s_cap = W->s_cap;
     int first = n - 1 - s_cap;
     if (first < W->win) first = W->win;
@@ -778,7 +784,7 @@ int orc_step(const orc_model* m, const orc_params* P, const int32_t* region_of_n
             if (P->col_cost > 0 && s_eff == s_cap) {
                 if (W->since + 1 >= every) {
                     const int can_grow = s_cap + d <= P->s && n - 1 - (s_cap + d) >= W->win;
-                    const int can_shrink = s_cap - d >= s_min;
+                    const int can_shrink = s_cap - d >= len_min;
                     int alt = 0;
                     if (W->grow_next && can_grow) alt = s_cap + d;
                     else if (can_shrink) alt = s_cap - d;

@@ -501,6 +501,10 @@ int run_solve(ebe_handle* h, const double* b, double* x, ebe_solve_stats* st) {
 
 int s_min_eff(const ebe_handle* h) { return std::max(1, std::min(h->cfg.s_min, h->cfg.s)); }
 
+// Shortest window length the probes may reach: s_min, but not below the
+// paper's lower end of s (8, or s itself when s < 8; Sec. 4, Fig. 3).
+int len_min_eff(const ebe_handle* h) { return std::max(s_min_eff(h), std::min(8, h->cfg.s)); }
+
 // Snapshot window of step n: AB errors e^first .. e^{n-1}, first = max(start,
 // n - 1 - s_cap); returns the column pairs s_eff = n - 1 - first when the map is
 // used (s_eff >= s_min), else 0.
@@ -521,7 +525,7 @@ int probe_length(const ebe_handle* h, int n, int s_eff) {
     if (c.fixed_window || c.col_cost < 0 || s_eff != h->ws.s_cap || h->ws.since + 1 < c.probe_every) return 0;
     const int s_cap = h->ws.s_cap, d = c.probe_step;
     const bool can_grow = s_cap + d <= c.s && n - 1 - (s_cap + d) >= h->ws.start;
-    const bool can_shrink = s_cap - d >= s_min_eff(h);
+    const bool can_shrink = s_cap - d >= len_min_eff(h);
     if (h->ws.grow_next && can_grow) return s_cap + d;
     if (can_shrink) return s_cap - d;
     if (can_grow) return s_cap + d;
@@ -808,7 +812,7 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     if (c.patch_elems <= 0) c.patch_elems = kMaxPatchElems;
     if (c.inner_iters <= 0) c.inner_iters = 16;
     if (c.inner_tol <= 0) c.inner_tol = 1e-2;
-    if (c.s_min <= 0) c.s_min = 8;
+    if (c.s_min <= 0) c.s_min = 3;
     if (c.probe_every <= 0) c.probe_every = 16;
     if (c.probe_step <= 0) c.probe_step = 8;
     if (c.skip_ratio == 0) c.skip_ratio = 0.01;

@@ -458,7 +458,7 @@ int ebe_batch_create(const ebe_config* cfg, void* stream, ebe_batch** out) {
     if (c.max_iter <= 0) c.max_iter = 10000;
     if (c.drop_tol <= 0) c.drop_tol = 1e-6;
     if (c.region_nodes <= 0) c.region_nodes = 512;
-    if (c.s_min <= 0) c.s_min = 8;
+    if (c.s_min <= 0) c.s_min = 3;
     if (!(c.dt > 0) || !(c.tol > 0) || c.s < 0 || c.s > kMaxCols - 1 || c.predictor < 0 || c.predictor > 2 ||
         c.rayleigh_alpha < 0 || c.rayleigh_beta < 0 || c.precision != EBE_PREC_FP64) {
         g_batch_create_error = "invalid configuration (need dt > 0, tol > 0, 0 <= s <= 32, predictor 0..2, FP64)";

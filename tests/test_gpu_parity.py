@@ -303,7 +303,7 @@ def _oracle_at(c, oracle_lib, vh, ring, it, win, u, v, a, **kw):
 
 @pytest.mark.parametrize("it,win", [(5, 1), (9, 1), (30, 1), (30, 20), (30, 25)])
 def test_predict_guarded_window_matches_oracle(small, oracle_lib, it, win):
-    """Default rule (s_min 8, AB4 guard) on an identical state and history: the same
+    """Default rule (s_min 3, AB4 guard) on an identical state and history: the same
     window, the same pick and both candidates' initial residuals as the oracle's."""
     m, sol, wl = small["model"], small["sol"], small["wl"]
     say("predict guarded it", it, "win", win)

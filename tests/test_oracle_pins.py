@@ -732,6 +732,19 @@ def test_probe_lengthens_the_window_when_the_longer_one_saves_trips(oracle_lib):
     assert rec2.probe == 0 or rec2.probe < 8
 
 
+def test_probes_keep_the_window_length_in_the_papers_range(oracle_lib):
+    """The map may start from one column pair (s_min = 1), but a probe never takes the
+    window below 8 pairs, the lower end of the paper's range of s: from 8 pairs with a
+    probe step of 4 the probe lengthens (12), from 12 it may shorten to exactly 8."""
+    for cap, expect in ((8, 12), (12, 8)):
+        st, rng, free, dreg, g, e_star = _exact_step(oracle_lib, 16, 40, 74)
+        st.P.s_min = 1
+        st.P.probe_step = 4
+        st.ws.s_cap, st.ws.rate, st.ws.grow_next = cap, 0.1, 0
+        rec, _, _ = st.step(g=g)
+        assert rec.s_eff == cap and rec.probe == expect
+
+
 def test_guard_skips_the_ab4_evaluation_while_the_map_is_far_ahead(oracle_lib):
     st, rng, free, dreg, g, e_star = _exact_step(oracle_lib, 16, 40, 74)
     n = 41

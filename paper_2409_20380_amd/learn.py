@@ -17,7 +17,7 @@ from . import ebe, inputs
 
 def generate(sol, wl, seeds, steps, nodes, capacity, log=None):
     """Run one trajectory per seed from rest, collecting samples at `nodes`
-    (int32 CUDA tensor of node ids) on every step whose snapshot window is full."""
+    (int32 CUDA tensor of node ids) on every step from the fifth on."""
     sol.set_predictor(ebe.PRED_SNAPSHOT)
     sol.collect(capacity, nodes)
     t0 = time.time()

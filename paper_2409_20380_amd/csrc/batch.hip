@@ -381,11 +381,9 @@ __device__ __forceinline__ void node_range(int64_t n, int b, int g, int64_t& lo,
 __device__ __forceinline__ void gather_slots(const DevNodes& N, const double* q, int64_t n, double& q0, double& q1,
                                              double& q2) {
     const int k0 = N.slot_ptr[n], k1 = N.slot_ptr[n + 1];
-    const double* s = q + 3 * (int64_t)k0;
+    double s[3];
+    sum_slots(q, k0, k1 - k0, s);
     q0 = s[0]; q1 = s[1]; q2 = s[2];
-    for (int k = 1; k < k1 - k0; ++k) {
-        q0 += s[3 * k]; q1 += s[3 * k + 1]; q2 += s[3 * k + 2];
-    }
 }
 
 // Trip j, update part for case blockIdx.y: alpha = rho_j / (p, A p), r -= alpha q,
@@ -404,20 +402,32 @@ __global__ __launch_bounds__(256) void k_bupdate(BNodeArgs A) {
         const double* q = A.qbuf + 3 * (int64_t)c * A.pn;
         int64_t lo, hi;
         node_range(A.N.n, blockIdx.x, gridDim.x, lo, hi);
+        // Every load of a node is issued before the first store (the stores to
+        // x, r and z could alias the later loads as far as the compiler knows).
         for (int64_t n = lo + threadIdx.x; n < hi; n += blockDim.x) {
-            double q0, q1, q2;
-            gather_slots(A.N, q, n, q0, q1, q2);
+            const int k0 = A.N.slot_ptr[n], ns = A.N.slot_ptr[n + 1] - k0;
             const uint8_t fm = A.N.fixmask[n];
-            if (fm & 1) q0 = 0.0;
-            if (fm & 2) q1 = 0.0;
-            if (fm & 4) q2 = 0.0;
             const int64_t i = off + 3 * n;
-            const double r0 = fma(-alpha, q0, A.r_[i]), r1 = fma(-alpha, q1, A.r_[i + 1]), r2 = fma(-alpha, q2, A.r_[i + 2]);
-            A.x[i] = fma(alpha, A.p[i], A.x[i]);
-            A.x[i + 1] = fma(alpha, A.p[i + 1], A.x[i + 1]);
-            A.x[i + 2] = fma(alpha, A.p[i + 2], A.x[i + 2]);
+            double rv[3], xv[3], pv[3], B[6];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                rv[d] = A.r_[i + d];
+                xv[d] = A.x[i + d];
+                pv[d] = A.p[i + d];
+            }
+#pragma unroll
+            for (int t = 0; t < 6; ++t) B[t] = A.binv6[6 * n + t];
+            double qv[3];
+            sum_slots(q, k0, ns, qv);
+            if (fm & 1) qv[0] = 0.0;
+            if (fm & 2) qv[1] = 0.0;
+            if (fm & 4) qv[2] = 0.0;
+            const double r0 = fma(-alpha, qv[0], rv[0]), r1 = fma(-alpha, qv[1], rv[1]), r2 = fma(-alpha, qv[2], rv[2]);
             double z0, z1, z2;
-            apply_binv(A.binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
+            apply_binv(B, r0, r1, r2, z0, z1, z2);
+            A.x[i] = fma(alpha, pv[0], xv[0]);
+            A.x[i + 1] = fma(alpha, pv[1], xv[1]);
+            A.x[i + 2] = fma(alpha, pv[2], xv[2]);
             A.r_[i] = r0; A.r_[i + 1] = r1; A.r_[i + 2] = r2;
             A.z[i] = z0; A.z[i + 1] = z1; A.z[i + 2] = z2;
             v0 += z0 * r0 + z1 * r1 + z2 * r2;
@@ -457,22 +467,26 @@ __global__ __launch_bounds__(256) void k_bresidual(BNodeArgs A, int mode) {
     int64_t lo, hi;
     node_range(A.N.n, blockIdx.x, gridDim.x, lo, hi);
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    // every load of a node before its first store
     for (int64_t n = lo + threadIdx.x; n < hi; n += blockDim.x) {
-        double q0, q1, q2;
-        gather_slots(A.N, q, n, q0, q1, q2);
+        const int k0 = A.N.slot_ptr[n], k1 = A.N.slot_ptr[n + 1];
         const uint8_t fm = A.N.fixmask[n];
         const int64_t i = off + 3 * n;
         const double b0 = A.b[i], b1 = A.b[i + 1], b2 = A.b[i + 2];
+        double B[6], qv[3];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) B[t] = A.binv6[6 * n + t];
+        sum_slots(q, k0, k1 - k0, qv);
         if (mode == 0 && fm) {
             if (fm & 1) A.x[i] = b0;
             if (fm & 2) A.x[i + 1] = b1;
             if (fm & 4) A.x[i + 2] = b2;
         }
-        const double r0 = (fm & 1) ? 0.0 : b0 - q0;
-        const double r1 = (fm & 2) ? 0.0 : b1 - q1;
-        const double r2 = (fm & 4) ? 0.0 : b2 - q2;
+        const double r0 = (fm & 1) ? 0.0 : b0 - qv[0];
+        const double r1 = (fm & 2) ? 0.0 : b1 - qv[1];
+        const double r2 = (fm & 4) ? 0.0 : b2 - qv[2];
         double z0, z1, z2;
-        apply_binv(A.binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
+        apply_binv(B, r0, r1, r2, z0, z1, z2);
         A.r_[i] = r0; A.r_[i + 1] = r1; A.r_[i + 2] = r2;
         A.z[i] = z0; A.z[i + 1] = z1; A.z[i + 2] = z2;
         v0 += z0 * r0 + z1 * r1 + z2 * r2;
@@ -523,16 +537,26 @@ __global__ __launch_bounds__(256) void k_bcombine(BNodeArgs A, const double* p, 
     const double* q = A.qbuf + 3 * (int64_t)c * A.pn;
     int64_t lo, hi;
     node_range(A.N.n, blockIdx.x, gridDim.x, lo, hi);
+    // every load of a node (unconditional for the launch's mode) before its first store
     for (int64_t n = lo + threadIdx.x; n < hi; n += blockDim.x) {
-        double s[3];
-        gather_slots(A.N, q, n, s[0], s[1], s[2]);
+        const int k0 = A.N.slot_ptr[n], k1 = A.N.slot_ptr[n + 1];
         const uint8_t fm = A.N.fixmask[n];
         const int64_t i = off + 3 * n;
+        double pv[3] = {0.0, 0.0, 0.0}, fv[3] = {0.0, 0.0, 0.0}, s[3];
+        if (mode == 1) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) pv[d] = p[i + d];
+        }
+        if (mode == 2 && f) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fv[d] = f[i + d];
+        }
+        sum_slots(q, k0, k1 - k0, s);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             double v = s[d];
-            if (mode == 1 && ((fm >> d) & 1)) v = p[i + d];
-            if (mode == 2) v = ((fm >> d) & 1) ? 0.0 : v + (f ? f[i + d] : 0.0);
+            if (mode == 1 && ((fm >> d) & 1)) v = pv[d];
+            if (mode == 2) v = ((fm >> d) & 1) ? 0.0 : v + fv[d];
             out[i + d] = v;
         }
     }

@@ -240,6 +240,29 @@ __device__ __forceinline__ void apply_binv(const T* B, T r0, T r1, T r2, T& z0, 
     z2 = B[4] * r0 + B[5] * r1 + B[2] * r2;
 }
 
+// Sum of the ns >= 1 matvec slots of one node starting at slot k0, in slot
+// order ((s0 + s1) + s2) + ...  The first two are loaded unconditionally (a
+// node with one slot reads its first twice), so that only nodes with three or
+// more slots run the loop.  Callers issue their other loads of the node
+// before this one: the slot values are the only ones that wait for the slot
+// range.
+template <class T>
+__device__ __forceinline__ void sum_slots(const T* qbuf, int k0, int ns, T (&q)[3]) {
+    const T* qs = qbuf + 3 * (int64_t)k0;
+    const int o1 = ns > 1 ? 3 : 0;
+    T qb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        q[c] = qs[c];
+        qb[c] = qs[o1 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[c] = ns > 1 ? q[c] + qb[c] : q[c];
+    for (int k = 2; k < ns; ++k) {
+        q[0] += qs[3 * k]; q[1] += qs[3 * k + 1]; q[2] += qs[3 * k + 2];
+    }
+}
+
 // Modes of the element kernels.
 enum { MODE_APPLY = 0, MODE_PCG = 1, MODE_RHS = 2 };
 

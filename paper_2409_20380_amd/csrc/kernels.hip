@@ -591,11 +591,9 @@ void launch_ebe_diag(hipStream_t s, const DevPatches& P, double cm, double ck, d
 template <class T>
 __device__ __forceinline__ void gather_q(const DevNodes& N, const T* qbuf, int64_t n, T& q0, T& q1, T& q2) {
     const int k0 = N.slot_ptr[n], k1 = N.slot_ptr[n + 1];
-    const T* q = qbuf + 3 * (int64_t)k0;
+    T q[3];
+    sum_slots(qbuf, k0, k1 - k0, q);
     q0 = q[0]; q1 = q[1]; q2 = q[2];
-    for (int k = 1; k < k1 - k0; ++k) {
-        q0 += q[3 * k]; q1 += q[3 * k + 1]; q2 += q[3 * k + 2];
-    }
 }
 
 // mode 0: q = sum (no constraint handling); mode 1: A_bc (free rows: sum, fixed: identity p)
@@ -707,21 +705,25 @@ __global__ __launch_bounds__(256) void k_residual(DevNodes N, const double* qbuf
         sc->x_base = 0;
     }
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    // every load of a node before its first store
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
-        double q0, q1, q2;
-        gather_q(N, qbuf, n, q0, q1, q2);
-        uint8_t fm = N.fixmask[n];
-        double b0 = b[3 * n], b1 = b[3 * n + 1], b2 = b[3 * n + 2];
+        const int k0 = N.slot_ptr[n], k1 = N.slot_ptr[n + 1];
+        const uint8_t fm = N.fixmask[n];
+        const double b0 = b[3 * n], b1 = b[3 * n + 1], b2 = b[3 * n + 2];
+        double B[6], q[3];
+#pragma unroll
+        for (int t = 0; t < 6; ++t) B[t] = binv6[6 * n + t];
+        sum_slots(qbuf, k0, k1 - k0, q);
         if (mode == 0 && fm) {  // fixed rows of A_bc are identity: x = b there, exactly
             if (fm & 1) x[3 * n] = b0;
             if (fm & 2) x[3 * n + 1] = b1;
             if (fm & 4) x[3 * n + 2] = b2;
         }
-        double r0 = (fm & 1) ? 0.0 : b0 - q0;
-        double r1 = (fm & 2) ? 0.0 : b1 - q1;
-        double r2 = (fm & 4) ? 0.0 : b2 - q2;
+        const double r0 = (fm & 1) ? 0.0 : b0 - q[0];
+        const double r1 = (fm & 2) ? 0.0 : b1 - q[1];
+        const double r2 = (fm & 4) ? 0.0 : b2 - q[2];
         double z0, z1, z2;
-        apply_binv(binv6 + 6 * n, r0, r1, r2, z0, z1, z2);
+        apply_binv(B, r0, r1, r2, z0, z1, z2);
         r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
         z[3 * n] = z0; z[3 * n + 1] = z1; z[3 * n + 2] = z2;
         v0 += z0 * r0 + z1 * r1 + z2 * r2;
@@ -772,10 +774,62 @@ void launch_check_finalize(hipStream_t s, DevScalars* sc, const double* res_part
     hipLaunchKernelGGL(k_check_finalize, dim3(1), dim3(256), 0, s, sc, res_part, g, j_next, tol);
 }
 
+// The node loop of the update for one x mode (XM 0: x untouched, the first
+// trip of a pair; 1: x += alpha p; 2: x += alpha p + alpha_prev p_other).
+// The mode is fixed per launch, so the loop has no branch around its loads:
+// every load of a node is issued before the first is consumed.
+template <class T, class S, int XM>
+__device__ __forceinline__ void pcg_update_nodes(const DevNodes& N, const T* qbuf, const S* p, const T* binv6, T* x,
+                                                 T* r, S* z, const S* p_other, T alpha, T alpha_prev, double& v0,
+                                                 double& v1) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += stride) {
+        const int k0 = N.slot_ptr[n], k1 = N.slot_ptr[n + 1];
+        const uint8_t fm = N.fixmask[n];
+        T rv[3], xv[3], pv[3], po[3], B[6];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            rv[c] = r[3 * n + c];
+            if (XM != 0) {
+                xv[c] = x[3 * n + c];
+                pv[c] = from_storage<T>(p[3 * n + c]);
+            }
+            if (XM == 2) po[c] = from_storage<T>(p_other[3 * n + c]);
+        }
+#pragma unroll
+        for (int t = 0; t < 6; ++t) B[t] = binv6[6 * n + t];
+        T q[3];
+        sum_slots(qbuf, k0, k1 - k0, q);
+        if (fm & 1) q[0] = T(0);
+        if (fm & 2) q[1] = T(0);
+        if (fm & 4) q[2] = T(0);
+        const T r0 = fma(-alpha, q[0], rv[0]);
+        const T r1 = fma(-alpha, q[1], rv[1]);
+        const T r2 = fma(-alpha, q[2], rv[2]);
+        if (XM == 2) {
+            x[3 * n] = fma(alpha, pv[0], fma(alpha_prev, po[0], xv[0]));
+            x[3 * n + 1] = fma(alpha, pv[1], fma(alpha_prev, po[1], xv[1]));
+            x[3 * n + 2] = fma(alpha, pv[2], fma(alpha_prev, po[2], xv[2]));
+        } else if (XM == 1) {
+            x[3 * n] = fma(alpha, pv[0], xv[0]);
+            x[3 * n + 1] = fma(alpha, pv[1], xv[1]);
+            x[3 * n + 2] = fma(alpha, pv[2], xv[2]);
+        }
+        T z0, z1, z2;
+        apply_binv(B, r0, r1, r2, z0, z1, z2);
+        r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
+        const S zs0 = to_storage<S>(z0), zs1 = to_storage<S>(z1), zs2 = to_storage<S>(z2);
+        z[3 * n] = zs0; z[3 * n + 1] = zs1; z[3 * n + 2] = zs2;
+        // dots in FP64 with the stored z (what the next matvec reads)
+        v0 += (double)from_storage<T>(zs0) * r0 + (double)from_storage<T>(zs1) * r1 + (double)from_storage<T>(zs2) * r2;
+        v1 += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
+    }
+}
+
 // Trip j, update part: alpha = rho_j / (p, A p) from the matvec partials,
 // r -= alpha q, x += alpha p, z = B^{-1} r, and partials of (z, r), (r, r)
 // for trip j + 1.  Compute type T, storage type S of p and z.  Persistent
-// grid-stride over nodes; two nodes per thread per trip with all loads first.
+// grid-stride over nodes, one node per thread per round.
 template <class T, class S>
 __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, const S* p, const T* binv6, T* x, T* r,
                                                     S* z, DevScalars* sc, const DevScalars* outer,
@@ -799,56 +853,9 @@ __global__ __launch_bounds__(256) void k_pcg_update(DevNodes N, const T* qbuf, c
     const T alpha_prev = pair ? (T)sc->x_alpha : T(0);
     if (defer && blockIdx.x == 0 && threadIdx.x == 0) sc->x_alpha = alpha_d;
     double v0 = 0.0, v1 = 0.0;
-    constexpr int U = 1;   // nodes per thread per trip (one: fewer registers, more waves in flight)
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t n0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n0 < N.n; n0 += U * stride) {
-        T q[U][3], rv[U][3], xv[U][3], pv[U][3], po[U][3], B[U][6];
-        uint8_t fm[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t n = n0 + u * stride;
-            const bool ok = n < N.n;
-            if (ok) gather_q(N, qbuf, n, q[u][0], q[u][1], q[u][2]);
-            fm[u] = ok ? N.fixmask[n] : 0;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                rv[u][c] = ok ? r[3 * n + c] : T(0);
-                xv[u][c] = (ok && !defer) ? x[3 * n + c] : T(0);
-                pv[u][c] = (ok && !defer) ? from_storage<T>(p[3 * n + c]) : T(0);
-                po[u][c] = (ok && pair) ? from_storage<T>(p_other[3 * n + c]) : T(0);
-            }
-#pragma unroll
-            for (int t = 0; t < 6; ++t) B[u][t] = ok ? binv6[6 * n + t] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t n = n0 + u * stride;
-            if (n >= N.n) continue;
-            if (fm[u] & 1) q[u][0] = T(0);
-            if (fm[u] & 2) q[u][1] = T(0);
-            if (fm[u] & 4) q[u][2] = T(0);
-            const T r0 = fma(-alpha, q[u][0], rv[u][0]);
-            const T r1 = fma(-alpha, q[u][1], rv[u][1]);
-            const T r2 = fma(-alpha, q[u][2], rv[u][2]);
-            if (pair) {
-                x[3 * n] = fma(alpha, pv[u][0], fma(alpha_prev, po[u][0], xv[u][0]));
-                x[3 * n + 1] = fma(alpha, pv[u][1], fma(alpha_prev, po[u][1], xv[u][1]));
-                x[3 * n + 2] = fma(alpha, pv[u][2], fma(alpha_prev, po[u][2], xv[u][2]));
-            } else if (!defer) {
-                x[3 * n] = fma(alpha, pv[u][0], xv[u][0]);
-                x[3 * n + 1] = fma(alpha, pv[u][1], xv[u][1]);
-                x[3 * n + 2] = fma(alpha, pv[u][2], xv[u][2]);
-            }
-            T z0, z1, z2;
-            apply_binv(B[u], r0, r1, r2, z0, z1, z2);
-            r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
-            const S zs0 = to_storage<S>(z0), zs1 = to_storage<S>(z1), zs2 = to_storage<S>(z2);
-            z[3 * n] = zs0; z[3 * n + 1] = zs1; z[3 * n + 2] = zs2;
-            // dots in FP64 with the stored z (what the next matvec reads)
-            v0 += (double)from_storage<T>(zs0) * r0 + (double)from_storage<T>(zs1) * r1 + (double)from_storage<T>(zs2) * r2;
-            v1 += (double)r0 * r0 + (double)r1 * r1 + (double)r2 * r2;
-        }
-    }
+    if (defer) pcg_update_nodes<T, S, 0>(N, qbuf, p, binv6, x, r, z, p_other, alpha, alpha_prev, v0, v1);
+    else if (pair) pcg_update_nodes<T, S, 2>(N, qbuf, p, binv6, x, r, z, p_other, alpha, alpha_prev, v0, v1);
+    else pcg_update_nodes<T, S, 1>(N, qbuf, p, binv6, x, r, z, p_other, alpha, alpha_prev, v0, v1);
     v0 = block_bcast_sum(v0);
     v1 = block_bcast_sum(v1);
     if (threadIdx.x == 0) {
@@ -939,13 +946,15 @@ __global__ __launch_bounds__(256) void k_inner_init(DevNodes N, const double* r6
     if (stop != DONE_RUNNING) return;
     double v0 = 0.0, v1 = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
+        // every load unconditional and before the first store
         const uint8_t fm = N.fixmask[n];
-        T r0 = (fm & 1) ? T(0) : (T)r64[3 * n];
-        T r1 = (fm & 2) ? T(0) : (T)r64[3 * n + 1];
-        T r2 = (fm & 4) ? T(0) : (T)r64[3 * n + 2];
+        const double a0 = r64[3 * n], a1 = r64[3 * n + 1], a2 = r64[3 * n + 2];
         T B[6];
 #pragma unroll
         for (int t = 0; t < 6; ++t) B[t] = binv6[6 * n + t];
+        const T r0 = (fm & 1) ? T(0) : (T)a0;
+        const T r1 = (fm & 2) ? T(0) : (T)a1;
+        const T r2 = (fm & 4) ? T(0) : (T)a2;
         T z0, z1, z2;
         apply_binv(B, r0, r1, r2, z0, z1, z2);
         r[3 * n] = r0; r[3 * n + 1] = r1; r[3 * n + 2] = r2;
@@ -1005,21 +1014,28 @@ __global__ __launch_bounds__(256) void k_outer_update(DevNodes N, const double* 
         return;
     }
     double v1 = 0.0;
+    // every load of a node before its first store (the stores could alias the
+    // later loads as far as the compiler knows)
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N.n; n += (int64_t)gridDim.x * blockDim.x) {
-        double q0, q1, q2;
-        gather_q(N, qbuf, n, q0, q1, q2);
+        const int k0 = N.slot_ptr[n], k1 = N.slot_ptr[n + 1];
         const uint8_t fm = N.fixmask[n];
-        if (fm & 1) q0 = 0.0;
-        if (fm & 2) q1 = 0.0;
-        if (fm & 4) q2 = 0.0;
-        const double qq[3] = {q0, q1, q2};
+        double ro[3], xv[3], pv[3], qq[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double ro = r[3 * n + c];
-            const double rn = fma(-alpha, qq[c], ro);
-            r_prev[3 * n + c] = ro;
+            ro[c] = r[3 * n + c];
+            xv[c] = x[3 * n + c];
+            pv[c] = p[3 * n + c];
+        }
+        sum_slots(qbuf, k0, k1 - k0, qq);
+        if (fm & 1) qq[0] = 0.0;
+        if (fm & 2) qq[1] = 0.0;
+        if (fm & 4) qq[2] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double rn = fma(-alpha, qq[c], ro[c]);
+            r_prev[3 * n + c] = ro[c];
             r[3 * n + c] = rn;
-            x[3 * n + c] = fma(alpha, p[3 * n + c], x[3 * n + c]);
+            x[3 * n + c] = fma(alpha, pv[c], xv[c]);
             v1 += rn * rn;
         }
     }

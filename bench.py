@@ -6,8 +6,10 @@ split into 6 straight 10-node tetrahedra: 1,081,665 nodes, 3,244,995 dof,
 786,432 elements; Newmark-beta (beta = 1/4, gamma = 1/2), dt = 0.01 s,
 Rayleigh damping 5 % at 0.1 and 2.5 Hz; bottom fixed; seeded band-limited
 base acceleration (0.1 - 2.5 Hz); initial guess = Adams-Bashforth 4 plus the
-regional snapshot predictor over the last 32 steps (regions of 8^3 lattice
-nodes); 3x3 block-Jacobi PCG to relative residual 1e-8.
+regional snapshot predictor over the last 32 steps (blocks of 8^3 lattice
+nodes order the nodes and shape the element patches; runs of 27 of them, in
+Morton order of their centroids, are the predictor's least-squares regions);
+3x3 block-Jacobi PCG to relative residual 1e-8.
 
 One bench step = one full time step (right-hand side, predictor, PCG refine,
 Newmark update) on inputs resident in HBM.  Prints ONE JSON line on stdout;
@@ -136,6 +138,9 @@ def main():
     ap.add_argument("--patch-elems", type=int, default=256, help="elements per EBE patch (1..256)")
     ap.add_argument("--region-block", type=int, default=0,
                     help="predictor regions of b^3 lattice nodes (0: the workload's, 8 = 512 nodes)")
+    ap.add_argument("--region-merge", type=int, default=-1,
+                    help="given regions merged per predictor region, in Morton order of their centroids "
+                         "(-1: the workload's, 1 = none)")
     ap.add_argument("--workload", choices=["plain", "large", "learned", "ensemble"], default="plain")
     ap.add_argument("--no-graph", action="store_true", help="ensemble: enqueue PCG trips without hipGraph")
     ap.add_argument("--no-tune", action="store_true", help="ensemble: default case tiles instead of the autotuner")
@@ -190,12 +195,14 @@ def main():
     wl_run = inputs.Workload(wl.name, cells=wl.cells, h=wl.h, dt=wl.dt, nt=nt, s=s_win, tol=wl.tol,
                              seed=wl.seed, region_block=args.region_block or wl.region_block)
     mesh, em, mat, fx, regions, wave = wl_run.build()
+    merge = args.region_merge if args.region_merge >= 0 else wl.region_merge
     dof = 3 * mesh.n_nodes
     log(f"mesh {wl.cells}: {mesh.n_nodes} nodes, {dof} dof, {mesh.n_elems} elements")
     aR, bR = wl.rayleigh
     sol = ebe.Solver(wl.dt, aR, bR, s=s_win, tol=wl.tol, patch_elems=args.patch_elems, precision=prec,
                      inner_iters=args.inner_iters, inner_tol=args.inner_tol, drop_tol=args.drop_tol,
-                     predictor=args.predictor, s_min=args.s_min, fixed_window=args.fixed_window)
+                     predictor=args.predictor, s_min=args.s_min, fixed_window=args.fixed_window,
+                     region_merge=merge)
     # per-step forcing, resident in HBM before the timed region: base acceleration (3 values
     # a step) or the paper-like surface impulses (a force vector a step)
     f_all = None
@@ -280,7 +287,7 @@ def main():
                                                                      ", guarded window")}[args.predictor],
                    "s_min": ecfg.s_min, "input": ("base acceleration" if args.input == "base" else
                                                   "surface impulses (284 points)"),
-                   "region_nodes": wl_run.region_block ** 3,
+                   "region_nodes": wl_run.region_block ** 3 * max(1, merge),
                    "drop_tol": drop,
                    "timed_steps": f"{args.warmup + 1}-{nt}",
                    "refine": ("block-Jacobi PCG, FP64" if args.precision == "fp64" else
@@ -301,11 +308,12 @@ def main():
                      "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy",
                      "bytes_per_launch": launch_bytes, "mean_launch_ms": ebe_ms, "timed_launches": n_timed},
     }
+    pred_regions, _ = sol.regions()   # the predictor's regions (merged ones when region_merge > 1)
     sol.close()
     if not args.no_cpu_baseline and args.workload == "plain" and args.input == "base" and args.predictor == 2 \
             and not args.snapshots and not args.s_min and not args.fixed_window:
         log(f"CPU baseline: oracle, {args.cpu_steps} steps")
-        out["cpu_baseline"] = cpu_baseline(wl_run, mesh, em, mat, fx, regions, wave, args.cpu_steps,
+        out["cpu_baseline"] = cpu_baseline(wl_run, mesh, em, mat, fx, pred_regions, wave, args.cpu_steps,
                                            gpu_iters=float(np.mean(iters)))
     print(json.dumps(out), flush=True)
 

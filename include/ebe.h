@@ -130,7 +130,16 @@ typedef struct {
                                trips, against which the probes weigh the trips a longer window
                                saves (0: 0.08, measured on the 64x64x32-cell mesh; < 0: no
                                probes, the length stays s) */
-    int32_t reserved[4];
+    int32_t region_merge;   /* <= 1: the predictor's regions are the regions ebe_assemble
+                               receives (or builds).  m > 1: those regions, ordered by the
+                               Morton code of their centroids, are merged m at a time into
+                               the regions of the snapshot map's least squares (Sec. 3.2:
+                               each region has its own fit), while the given regions keep
+                               ordering the nodes and so shaping the element patches: small
+                               compact regions give compact patches, merged ones give each
+                               fit more rows per column.  ebe_get_regions reports the
+                               merged regions. */
+    int32_t reserved[3];
 } ebe_config;
 
 typedef struct {

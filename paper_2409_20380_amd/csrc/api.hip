@@ -862,7 +862,7 @@ int ebe_assemble(ebe_handle* h, int64_t n_nodes, const double* coords, int64_t n
         Topology& T = h->T;
         std::string e = build_topology(T, n_nodes, coords, n_elems, conn, elem_mat, n_mat, mat, fixed,
                                        region_of_node, h->cfg.region_nodes, h->cfg.patch_elems,
-                                       ebe_patch_lds(n_mat));
+                                       ebe_patch_lds(n_mat), h->cfg.region_merge);
         if (!e.empty()) throw Arg{e};
         hipStream_t s = h->stream;
         const int64_t N = T.n_nodes, n3 = 3 * N;

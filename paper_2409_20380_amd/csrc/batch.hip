@@ -293,15 +293,14 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_bebe(BEbeArgs A) {
                 continue;
             }
             DevScalars* sc = A.sc + c;
-            double zr = 0.0, rr = 0.0, bb = 0.0;
-            if (tid < g) {
+            double zr = 0.0, rr = 0.0, bb = 0.0, unused = 0.0;
+            if (tid < g) {   // the (b, b) array exists in both slots: read with the others, used on trip 0
                 zr = A.upd_part[upd_index(j, 0, c, tid, A.r, g)];
                 rr = A.upd_part[upd_index(j, 1, c, tid, A.r, g)];
-                if (j == 0) bb = A.upd_part[upd_index(j, 2, c, tid, A.r, g)];
+                bb = A.upd_part[upd_index(j, 2, c, tid, A.r, g)];
             }
-            zr = block_bcast_sum(zr);
-            rr = block_bcast_sum(rr);
-            bb = block_bcast_sum(bb);
+            block_bcast_sum4(zr, rr, bb, unused);
+            if (j != 0) bb = 0.0;
             int stop = sc->done;
             double beta = 0.0;
             if (stop == DONE_RUNNING) {

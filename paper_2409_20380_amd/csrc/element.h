@@ -46,10 +46,13 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 template <int PER>
 __device__ __forceinline__ double lane_partials(const double* __restrict__ p, int n, int lane, int nlanes) {
     double v[PER];
+    // loads unconditional (index clamped into [0, n), n >= 1), so that the
+    // partials of several arrays are in flight together
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int i = lane + k * nlanes;
-        v[k] = i < n ? p[i] : 0.0;
+        const double t = p[i < n ? i : n - 1];
+        v[k] = i < n ? t : 0.0;
     }
     double s = 0.0;
 #pragma unroll
@@ -277,6 +280,25 @@ __device__ __forceinline__ double block_bcast_sum(double v) {
     if (threadIdx.x == 0) out = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return out;
+}
+
+// Four block sums at once (each in the fixed order of block_bcast_sum, so the
+// results are bitwise those of four separate calls), with one pair of barriers.
+__device__ __forceinline__ void block_bcast_sum4(double& a, double& b, double& c, double& d) {
+    __shared__ double red4[4][4];
+    __shared__ double out4[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const double s0 = wave_sum(a), s1 = wave_sum(b), s2 = wave_sum(c), s3 = wave_sum(d);
+    if (lane == 0) {
+        red4[0][w] = s0; red4[1][w] = s1; red4[2][w] = s2; red4[3][w] = s3;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int k = threadIdx.x;
+        out4[k] = (red4[k][0] + red4[k][1]) + (red4[k][2] + red4[k][3]);
+    }
+    __syncthreads();
+    a = out4[0]; b = out4[1]; c = out4[2]; d = out4[3];
 }
 
 // True-residual check is due when the loop stopped (converged or capped) and

@@ -333,7 +333,8 @@ static void device_limits(int& cus, int& lds_cu) {
 }
 
 // The patch builder's LDS limit: the element pass of the PCG loop keeps two
-// workgroups per CU.
+// workgroups per CU (its static shared memory, 200 bytes, within the reserve).
+constexpr int64_t kStaticLdsReserve = 256;
 PatchLds ebe_patch_lds(int32_t n_mat) {
     int cus = 0, lds_cu = 0;
     device_limits(cus, lds_cu);
@@ -346,7 +347,7 @@ PatchLds ebe_patch_lds(int32_t n_mat) {
     z.max_pn = 0;
     z.max_nv = 1;
     L.per_vertex = (int64_t)ebe_lds_bytes(z, MODE_PCG) - L.fixed;
-    L.budget = lds_cu / 2;
+    L.budget = lds_cu / 2 - kStaticLdsReserve;
     return L;
 }
 
@@ -406,14 +407,15 @@ __global__ __launch_bounds__(64 * kEbeWaves, 2) void k_ebe_pcg(PcgEbeArgs A) {
     const int tid = threadIdx.x;
     const int j = A.j;
     const int g = A.g_res;
+    // the four partial arrays of the slot exist whether used or not: all are
+    // read together and the unused sums discarded
     double zr = lane_partials<kMaxResGrid / NT>(A.res_part, g, tid, NT);
     double rr = lane_partials<kMaxResGrid / NT>(A.res_part + g, g, tid, NT);
-    double bb = j == 0 ? lane_partials<kMaxResGrid / NT>(A.res_part + 2 * g, g, tid, NT) : 0.0;
-    double zp = (FLEX && j != sc->cycle_start) ? lane_partials<kMaxResGrid / NT>(A.res_part + 3 * g, g, tid, NT) : 0.0;
-    zr = block_bcast_sum(zr);
-    rr = block_bcast_sum(rr);
-    bb = block_bcast_sum(bb);
-    if (FLEX) zp = block_bcast_sum(zp);
+    double bb = lane_partials<kMaxResGrid / NT>(A.res_part + 2 * g, g, tid, NT);
+    double zp = lane_partials<kMaxResGrid / NT>(A.res_part + 3 * g, g, tid, NT);
+    block_bcast_sum4(zr, rr, bb, zp);
+    if (j != 0) bb = 0.0;
+    if (!FLEX || j == sc->cycle_start) zp = 0.0;
     const double bnorm = (j == 0) ? sqrt(bb) : sc->bnorm;
     const double res = bnorm > 0.0 ? sqrt(rr) / bnorm : 0.0;
     int stop = DONE_RUNNING;

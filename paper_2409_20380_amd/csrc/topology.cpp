@@ -1,8 +1,10 @@
 // topology.cpp -- host-side preprocessing of the mesh for the EBE kernels.
 //
-// Internal node order: nodes sorted by (predictor region, Morton code of the
-// position), so every region is one contiguous range of the state vectors and
-// nodes that are close in space are close in memory.
+// Internal node order: nodes sorted by (region, Morton code of the position),
+// so every region is one contiguous range of the state vectors and nodes that
+// are close in space are close in memory.  With merging, the regions are
+// taken in the Morton order of their centroids and each run of region_merge
+// of them is one predictor region (contiguous too).
 // Element order: by the lowest internal id among the element's vertices,
 // ties broken by the Morton code of the centroid.  Consecutive runs of
 // patch_elems elements form a patch (inside a patch the elements are dealt
@@ -180,7 +182,7 @@ void region_chunks(const std::vector<int32_t>& region_start, std::vector<int32_t
 
 std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, const int32_t* conn,
                            const int32_t* elem_mat, int32_t n_mat, const double* mat, const uint8_t* fixed,
-                           const int32_t* region_of_node, int region_nodes, int patch_elems, const PatchLds& lds) {
+                           const int32_t* region_of_node, int region_nodes, int patch_elems, const PatchLds& lds, int region_merge) {
     if (N <= 0 || E <= 0) return "mesh must have nodes and elements";
     if (N >= (int64_t)1 << 31 || E >= (int64_t)1 << 31) return "mesh too large for 32-bit ids";
     if (n_mat <= 0 || n_mat > 65535) return "n_mat must be in [1, 65535]";
@@ -270,13 +272,43 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
         for (int64_t k = 0; k < N; ++k) T.region_user[ord[k]] = (int32_t)std::min<int64_t>(k / region_nodes, nr - 1);
     }
 
-    // ---- internal node order: (region, Morton)
+    // ---- merged predictor regions: the given regions in Morton order of
+    // their centroids, region_merge at a time; rank[r] is region r's position
+    // in that order (the identity without merging)
+    std::vector<int64_t> rank(T.n_regions);
+    std::iota(rank.begin(), rank.end(), 0);
+    if (region_merge > 1 && T.n_regions > 1) {
+        const int32_t R = T.n_regions;
+        std::vector<double> cen(3 * (size_t)R, 0.0);
+        std::vector<int64_t> cnt(R, 0);
+        for (int64_t v = 0; v < N; ++v) {
+            const int32_t r = T.region_user[v];
+            for (int d = 0; d < 3; ++d) cen[3 * (size_t)r + d] += X[3 * v + d];
+            cnt[r]++;
+        }
+        std::vector<uint64_t> rmort(R);
+        for (int32_t r = 0; r < R; ++r) {
+            for (int d = 0; d < 3; ++d) cen[3 * (size_t)r + d] /= (double)cnt[r];
+            rmort[r] = box.morton(&cen[3 * (size_t)r]);
+        }
+        std::vector<int32_t> rord(R);
+        std::iota(rord.begin(), rord.end(), 0);
+        std::stable_sort(rord.begin(), rord.end(), [&](int32_t a, int32_t b) { return rmort[a] < rmort[b]; });
+        for (int32_t k = 0; k < R; ++k) rank[rord[k]] = k;
+    }
+
+    // ---- internal node order: (given region in merge order, Morton)
     T.i2u.resize(N);
     std::iota(T.i2u.begin(), T.i2u.end(), 0);
     std::stable_sort(T.i2u.begin(), T.i2u.end(), [&](int32_t a, int32_t b) {
-        if (T.region_user[a] != T.region_user[b]) return T.region_user[a] < T.region_user[b];
+        const int64_t ra = rank[T.region_user[a]], rb = rank[T.region_user[b]];
+        if (ra != rb) return ra < rb;
         return mort[a] < mort[b];
     });
+    if (region_merge > 1 && T.n_regions > 1) {
+        for (int64_t v = 0; v < N; ++v) T.region_user[v] = (int32_t)(rank[T.region_user[v]] / region_merge);
+        T.n_regions = (int32_t)((T.n_regions + region_merge - 1) / region_merge);
+    }
     T.u2i.resize(N);
     for (int64_t i = 0; i < N; ++i) T.u2i[T.i2u[i]] = (int32_t)i;
     T.region_start.assign(T.n_regions + 1, 0);
@@ -314,21 +346,27 @@ std::string build_topology(Topology& T, int64_t N, const double* X, int64_t E, c
     });
 
     // ---- patches: cut the element order into runs of at most patch_elems
-    // elements whose nodes fit the LDS budget
+    // elements whose nodes fit the LDS budget.  The kernels size LDS by the
+    // largest node count and the largest vertex count over all patches (which
+    // may come from different patches), so a patch is closed once it would
+    // raise that combined size past the budget.
     std::vector<int64_t> cut(1, 0);
     {
         std::vector<int64_t> mark(N, -1);   // last patch that listed the node
-        int64_t npn = 0, nvx = 0, cnt = 0;
+        int64_t npn = 0, nvx = 0, cnt = 0, max_n = 0, max_v = 0;
         for (int64_t k = 0; k < E; ++k) {
             const int32_t* c = conn + 10 * (int64_t)eord[k];
             const int64_t cur = (int64_t)cut.size() - 1;
             int64_t add_n = 0, add_v = 0;
             for (int i = 0; i < 10; ++i)
                 if (mark[c[i]] != cur) { ++add_n; add_v += i < 4; }
-            const bool over = lds.budget > 0 &&
-                              lds.fixed + lds.per_node * (npn + add_n) + lds.per_vertex * (nvx + add_v) > lds.budget;
+            const bool over = lds.budget > 0 && lds.fixed + lds.per_node * std::max(max_n, npn + add_n) +
+                                                        lds.per_vertex * std::max(max_v, nvx + add_v) >
+                                                    lds.budget;
             if (cnt > 0 && (cnt == patch_elems || over)) {
                 cut.push_back(k);
+                max_n = std::max(max_n, npn);
+                max_v = std::max(max_v, nvx);
                 npn = nvx = cnt = 0;
                 add_n = 10;
                 add_v = 4;

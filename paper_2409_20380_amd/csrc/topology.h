@@ -71,10 +71,13 @@ struct PatchLds {
 
 // Builds the topology; returns an empty string on success or an error message.
 // Patches take consecutive elements of the spatial element order, at most
-// patch_elems of them and within lds.
+// patch_elems of them and within lds.  region_merge > 1 merges the given
+// regions, in Morton order of their centroids, region_merge at a time into
+// the predictor's regions (T.region_user); the given regions still order the
+// nodes.
 std::string build_topology(Topology& T, int64_t n_nodes, const double* coords, int64_t n_elems,
                            const int32_t* conn, const int32_t* elem_mat, int32_t n_mat, const double* mat,
                            const uint8_t* fixed, const int32_t* region_of_node, int region_nodes,
-                           int patch_elems, const PatchLds& lds = PatchLds());
+                           int patch_elems, const PatchLds& lds = PatchLds(), int region_merge = 1);
 
 }  // namespace ebe

@@ -37,7 +37,7 @@ class Config(C.Structure):
                 ("patch_elems", C.c_int32), ("chunk_iters", C.c_int32), ("precision", C.c_int32),
                 ("inner_iters", C.c_int32), ("s_min", C.c_int32), ("fixed_window", C.c_int32),
                 ("probe_every", C.c_int32), ("probe_step", C.c_int32), ("skip_ratio", C.c_double),
-                ("col_cost", C.c_double), ("reserved", C.c_int32 * 4)]
+                ("col_cost", C.c_double), ("region_merge", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Window(C.Structure):
@@ -201,14 +201,15 @@ class Solver:
     def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
                  max_iter=10000, drop_tol=0.0, region_nodes=512, patch_elems=256, chunk_iters=0, precision=PREC_FP64,
                  inner_iters=0, inner_tol=0.0, s_min=0, fixed_window=False, skip_ratio=0.0, col_cost=0.0,
-                 probe_every=0, probe_step=0, stream=None):
+                 probe_every=0, probe_step=0, region_merge=0, stream=None):
         import torch
         L = lib()
         cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol,
                      drop_tol=drop_tol, max_iter=max_iter, s=s, predictor=predictor, region_nodes=region_nodes,
                      patch_elems=patch_elems, chunk_iters=chunk_iters, precision=precision,
                      inner_iters=inner_iters, inner_tol=inner_tol, s_min=s_min, fixed_window=int(bool(fixed_window)),
-                     skip_ratio=skip_ratio, col_cost=col_cost, probe_every=probe_every, probe_step=probe_step)
+                     skip_ratio=skip_ratio, col_cost=col_cost, probe_every=probe_every, probe_step=probe_step,
+                     region_merge=region_merge)
         self.cfg = cfg
         if stream is None:
             stream = torch.cuda.current_stream()

@@ -289,6 +289,7 @@ class Workload:
     zeta: float = 0.05
     f_band: tuple = (0.1, 2.5)
     region_block: int = 8
+    region_merge: int = 1   # given regions per predictor region (the library's region_merge)
 
     @property
     def rayleigh(self):
@@ -310,8 +311,8 @@ SMALL = Workload("box8x8x8_p2tet_fp64", cells=(8, 8, 8), nt=100, s=16)
 # learned predictor: training and test waves of the headline mesh
 LEARN_TRAIN_SEEDS = tuple(range(100, 150))
 LEARN_TEST_SEEDS = tuple(range(200, 232))
-PLAIN = Workload("box64x64x32_p2tet_fp64", cells=(64, 64, 32), nt=1000, s=32)
-LARGE = Workload("box128x128x64_p2tet", cells=(128, 128, 64), nt=300, s=32)
+PLAIN = Workload("box64x64x32_p2tet_fp64", cells=(64, 64, 32), nt=1000, s=32, region_merge=27)
+LARGE = Workload("box128x128x64_p2tet", cells=(128, 128, 64), nt=300, s=32, region_merge=27)
 WORKLOADS = {"plain": PLAIN, "large": LARGE, "small": SMALL}
 # batched ensemble: (cells, cases) per mesh; cases take seeds 1..64 in order
 ENSEMBLE = (((16, 16, 8), 20), ((32, 32, 16), 24), ((48, 48, 24), 20))

@@ -520,6 +520,37 @@ def test_trajectory_matches_oracle(case, request, oracle_lib):
     sol.close()
 
 
+def test_trajectory_with_merged_regions(small, oracle_lib):
+    """Merged predictor regions (region_merge 8 over 64 given regions of 4^3 lattice nodes): every merged
+    region is the union of 8 whole given regions, and the merged map the library reports is the partition
+    the oracle's least squares uses; trajectory, residuals, decisions and trips as for given regions."""
+    from paper_2409_20380_amd import ebe, inputs as inp
+    c = small
+    wl, mesh = c["wl"], c["mesh"]
+    given = inp.block_regions(mesh, 4)
+    R = int(given.max()) + 1
+    say("trajectory with merged regions:", R, "given regions, 8 per predictor region")
+    sol = ebe.Solver(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol, region_merge=8)
+    sol.assemble(mesh.coords, mesh.conn, c["em"], c["mat"], c["fx"], given)
+    merged, nr = sol.regions()
+    assert R == 64 and nr == 8
+    of = [set(merged[given == r].tolist()) for r in range(R)]
+    assert all(len(x) == 1 for x in of)
+    assert np.bincount([next(iter(x)) for x in of], minlength=nr).tolist() == [8] * nr
+    cm = dict(c, regions=merged)
+    dg, do = [], []
+    U, its, res = _gpu_run(sol, c["wave"], wl.nt, dg)
+    Uref, _ = _oracle_run(cm, oracle_lib, 1e-13, wl.nt)
+    U8, its8 = _oracle_run(cm, oracle_lib, wl.tol, wl.nt, decisions=do)
+    err = np.linalg.norm(U - Uref) / np.linalg.norm(Uref)
+    say("space-time rel L2 vs tight oracle", err, "iters gpu/oracle", its.mean(), its8.mean())
+    assert err < TRAJ_TOL
+    assert (res < wl.tol).all()
+    assert dg == do
+    assert np.abs(its - its8).max() <= 2
+    sol.close()
+
+
 def test_bitwise_determinism_and_checkpoint(small):
     from paper_2409_20380_amd import ebe
     c = small

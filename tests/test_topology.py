@@ -204,31 +204,93 @@ LDS_COEF = (120, 24, 48)
 
 @pytest.mark.parametrize("budget", [81920, 40000, 20000])
 def test_patch_lds_budget(probe, budget):
-    """Patches close before their nodes would exceed the LDS budget; with a budget the natural 256-element
-    patches fit, nothing changes."""
+    """The kernels size LDS by the largest node count and the largest vertex count over all patches; the
+    builder closes a patch before that combined size would exceed the budget.  With a budget the natural
+    256-element patches fit, nothing changes."""
     per_node, per_vertex, fixed_b = LDS_COEF
     free = build(probe, inputs.SMALL, 256)
     t = build(probe, inputs.SMALL, 256, lds=(per_node, per_vertex, fixed_b, budget))
-    need = [fixed_b + per_node * (n1 - n0) + per_vertex * int(t["nv"][p]) for p, e0, e1, n0, n1 in patches(t)]
-    assert max(need) <= budget
+    sizes = [(n1 - n0, int(t["nv"][p])) for p, e0, e1, n0, n1 in patches(t)]
+    combined = lambda sz: fixed_b + per_node * max(n for n, v in sz) + per_vertex * max(v for n, v in sz)
+    assert combined(sizes) <= budget
     counts = [e1 - e0 for p, e0, e1, n0, n1 in patches(t) if e1 > e0]
     assert sum(counts) == len(t["conn"]) and max(counts) <= 256
-    natural = max(fixed_b + per_node * (n1 - n0) + per_vertex * int(free["nv"][p])
-                  for p, e0, e1, n0, n1 in patches(free))
+    natural = combined([(n1 - n0, int(free["nv"][p])) for p, e0, e1, n0, n1 in patches(free)])
     if natural <= budget:
         assert t["npat"] == free["npat"] and (t["el_ptr"] == free["el_ptr"]).all()
     else:
         assert t["npat"] > free["npat"]
-        # a patch is closed only when the next element would not fit
+        # a patch is closed only when the next element would raise the combined size past the budget
         conn, i2u = t["conn"], t["i2u"]
+        max_n = max_v = 0
         for p, e0, e1, n0, n1 in patches(t):
-            if p + 1 >= t["npat"] or e1 - e0 == 256:
+            if p + 1 >= t["npat"]:
                 continue
-            ent = t["nodes"][n0:n1] & ~np.uint32(OWNER)
-            users = set(int(i2u[v]) for v in ent)
-            nxt = t["lids"][e1]   # local ids of the next patch's first element, in the next patch
-            m0, m1 = t["pn_ptr"][p + 1], t["pn_ptr"][p + 2]
-            nxt_users = [int(i2u[int(t["nodes"][m0 + int(l)] & ~np.uint32(OWNER))]) for l in nxt]
-            add = [u for u in nxt_users if u not in users]
-            add_v = sum(1 for i, u in enumerate(nxt_users) if u not in users and i < 4)
-            assert fixed_b + per_node * (n1 - n0 + len(add)) + per_vertex * (int(t["nv"][p]) + add_v) > budget
+            if e1 - e0 < 256:
+                ent = t["nodes"][n0:n1] & ~np.uint32(OWNER)
+                users = set(int(i2u[v]) for v in ent)
+                nxt = t["lids"][e1]   # local ids of the next patch's first element, in the next patch
+                m0, m1 = t["pn_ptr"][p + 1], t["pn_ptr"][p + 2]
+                nxt_users = [int(i2u[int(t["nodes"][m0 + int(l)] & ~np.uint32(OWNER))]) for l in nxt]
+                add = [u for u in nxt_users if u not in users]
+                add_v = sum(1 for i, u in enumerate(nxt_users) if u not in users and i < 4)
+                assert (fixed_b + per_node * max(max_n, n1 - n0 + len(add)) +
+                        per_vertex * max(max_v, int(t["nv"][p]) + add_v)) > budget
+            max_n, max_v = max(max_n, n1 - n0), max(max_v, int(t["nv"][p]))
+
+
+def _morton_codes(p, lo, hi):
+    """Morton codes of points p [n, 3] in the box [lo, hi] (21 bits per axis, x in the lowest bit)."""
+    t = np.where(hi > lo, (p - lo) / np.where(hi > lo, hi - lo, 1.0), 0.0)
+    q = np.clip(np.floor(t * 2097151.0), 0, 2097151).astype(np.uint64)
+    out = np.zeros(len(p), np.uint64)
+    for b in range(21):
+        for d in range(3):
+            out |= ((q[:, d] >> np.uint64(b)) & np.uint64(1)) << np.uint64(3 * b + d)
+    return out
+
+
+@pytest.mark.parametrize("merge", [2, 3, 8])
+def test_region_merge(probe, merge):
+    """Merged predictor regions: the given regions, ordered by the Morton code of their centroids, merged
+    `merge` at a time; each merged region is one contiguous range of the internal order; the patches are
+    as compact as without merging (the given regions still order the nodes)."""
+    wl = inputs.Workload("box8x8x8_rb4", cells=(8, 8, 8), nt=1, s=1, region_block=4)
+    mesh, em, mat, fx, given, _ = wl.build()
+    a = lambda x, t: np.ascontiguousarray(x, dtype=t)
+    P = lambda x: x.ctypes.data_as(C.c_void_p)
+    xyz, conn = a(mesh.coords, np.float64), a(mesh.conn, np.int32)
+    args = lambda m: (C.c_int64(mesh.n_nodes), P(xyz), C.c_int64(len(conn)), P(conn), P(a(em, np.int32)),
+                      C.c_int(len(mat)), P(a(mat, np.float64)), P(a(fx, np.uint8)), P(a(given, np.int32)),
+                      C.c_int(512), C.c_int(256), *(C.c_int64(v) for v in (120, 24, 48, 81920)), C.c_int(m))
+    R = int(given.max()) + 1
+    stats = {}
+    for m in (1, merge):
+        assert probe.probe_build_merge(*args(m)) == 0
+        ru = np.zeros(mesh.n_nodes, np.int32)
+        rs = np.zeros(R + 2, np.int32)
+        nr = probe.probe_regions(P(ru), P(rs), C.c_int32(R + 2))
+        sz = np.zeros(7, np.int64)
+        probe.probe_sizes(P(sz))
+        i2u = np.zeros(mesh.n_nodes, np.int32)
+        el_ptr = np.zeros(sz[1] + 1, np.int32); pn_ptr = np.zeros(sz[1] + 1, np.int32); nv = np.zeros(sz[1], np.int32)
+        nodes = np.zeros(sz[2], np.uint32); slot = np.zeros(sz[2], np.int32); lids = np.zeros((sz[3], 10), np.uint16)
+        slot_ptr = np.zeros(mesh.n_nodes + 1, np.int32)
+        probe.probe_arrays(P(el_ptr), P(pn_ptr), P(nv), P(nodes), P(slot), P(lids), P(slot_ptr), P(i2u))
+        stats[m] = (nr, ru.copy(), rs[:nr + 1].copy(), i2u.copy(), sz[2] / mesh.n_nodes)
+    nr1, ru1, _, _, slots1 = stats[1]
+    assert nr1 == R and (ru1 == given).all()
+    nr, ru, rs, i2u, slots = stats[merge]
+    assert nr == (R + merge - 1) // merge
+    # the given regions in Morton order of their centroids, merged `merge` at a time
+    cen = np.array([mesh.coords[given == r].mean(0) for r in range(R)])
+    lo, hi = mesh.coords.min(0), mesh.coords.max(0)
+    order = np.argsort(_morton_codes(cen, lo, hi), kind="stable")
+    want = np.empty(R, np.int64)
+    want[order] = np.arange(R) // merge
+    assert (ru == want[given]).all()
+    # contiguous ranges of the internal order
+    assert rs[0] == 0 and rs[-1] == mesh.n_nodes
+    for r in range(nr):
+        assert (ru[i2u[rs[r]:rs[r + 1]]] == r).all()
+    assert slots <= 1.02 * slots1

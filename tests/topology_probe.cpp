@@ -37,6 +37,31 @@ extern "C" int probe_build_lds(int64_t nn, const double* xyz, int64_t ne, const 
     return e.empty() ? 0 : 1;
 }
 
+// As probe_build_lds, with region_merge.
+extern "C" int probe_build_merge(int64_t nn, const double* xyz, int64_t ne, const int32_t* conn, const int32_t* em,
+                                 int nm, const double* mat, const uint8_t* fx, const int32_t* reg, int region_nodes,
+                                 int patch_elems, int64_t per_node, int64_t per_vertex, int64_t fixed_bytes,
+                                 int64_t budget, int region_merge) {
+    g_T = Topology();
+    PatchLds lds;
+    lds.per_node = per_node;
+    lds.per_vertex = per_vertex;
+    lds.fixed = fixed_bytes;
+    lds.budget = budget;
+    std::string e =
+        build_topology(g_T, nn, xyz, ne, conn, em, nm, mat, fx, reg, region_nodes, patch_elems, lds, region_merge);
+    return e.empty() ? 0 : 1;
+}
+
+// Predictor regions: the region of every user node [nn], the count, and the
+// internal ranges region_start [n_regions + 1] (room for cap entries).
+extern "C" int32_t probe_regions(int32_t* region_user, int32_t* region_start, int32_t cap) {
+    std::memcpy(region_user, g_T.region_user.data(), g_T.region_user.size() * 4);
+    if ((int32_t)g_T.region_start.size() <= cap)
+        std::memcpy(region_start, g_T.region_start.data(), g_T.region_start.size() * 4);
+    return g_T.n_regions;
+}
+
 // sizes: n_patches, n_patches_pad, PN (patch-node entries), E, max_pn, max_nv, n_slots
 extern "C" void probe_sizes(int64_t* out) {
     out[0] = g_T.n_patches;

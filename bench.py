@@ -463,7 +463,8 @@ def run_ensemble(args):
     C = sum(r for _, r in inputs.ENSEMBLE)
     waves = [inputs.base_wave(1 + c, nt, dt) for c in range(C)]
     dof_total = sum(3 * m[2].n_nodes * m[1] for m in meshes)
-    batch = ebe.Batch(dt, aR, bR, s=s, tol=tol)
+    merge = args.region_merge if args.region_merge >= 0 else inputs.ENSEMBLE_REGION_MERGE
+    batch = ebe.Batch(dt, aR, bR, s=s, tol=tol, region_merge=merge)
     for cells, r, mesh, em, mat, fx, regions in meshes:
         batch.add_mesh(mesh.coords, mesh.conn, em, mat, fx, regions, r)
     t1 = time.time()
@@ -497,7 +498,7 @@ def run_ensemble(args):
     c0 = 0
     seq_detail = []
     for cells, r, mesh, em, mat, fx, regions in meshes:
-        sol = ebe.Solver(dt, aR, bR, s=s, tol=tol)
+        sol = ebe.Solver(dt, aR, bR, s=s, tol=tol, region_merge=merge)
         sol.assemble(mesh.coords, mesh.conn, em, mat, fx, regions)
         for it in range(1, args.warmup + 1):
             sol.step(base_acc=waves[c0][it])
@@ -526,7 +527,7 @@ def run_ensemble(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "ensemble_64_cases_3_meshes", "meshes": [[list(c), r] for c, r in inputs.ENSEMBLE],
-                   "dof_per_step": dof_total, "snapshots": s, "tol": tol, "seeds": "1-64",
+                   "dof_per_step": dof_total, "snapshots": s, "tol": tol, "seeds": "1-64", "region_merge": merge,
                    "graph": not args.no_graph, "tuned": not args.no_tune, "groups": groups},
         "cg_iters_per_step_per_case": float(iters.mean()),
         "max_true_rel_residual": res,

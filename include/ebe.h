@@ -107,7 +107,7 @@ typedef struct {
                                (<= 0: adaptive) */
     int32_t precision;      /* EBE_PREC_*: how Algorithm 1 is run (see below) */
     int32_t inner_iters;    /* mixed precision: inner PCG trips per outer trip at most
-                               (<= 0: 16) */
+                               (<= 0: 12) */
     int32_t s_min;          /* snapshot map used once its window holds at least
                                min(s_min, s) column pairs (<= 0: 3; the guard below keeps
                                AB4 where the short map is worse); AB4 alone before.  The
@@ -138,7 +138,8 @@ typedef struct {
                                ordering the nodes and so shaping the element patches: small
                                compact regions give compact patches, merged ones give each
                                fit more rows per column.  ebe_get_regions reports the
-                               merged regions. */
+                               merged regions.  The batch (ebe_batch_*) merges each mesh's
+                               regions the same way. */
     int32_t reserved[3];
 } ebe_config;
 

@@ -810,7 +810,7 @@ int ebe_create(const ebe_config* cfg, void* stream, ebe_handle** out) {
     if (c.drop_tol <= 0) c.drop_tol = c.precision == EBE_PREC_FP64 ? 1e-6 : 1e-5;
     if (c.region_nodes <= 0) c.region_nodes = 512;
     if (c.patch_elems <= 0) c.patch_elems = kMaxPatchElems;
-    if (c.inner_iters <= 0) c.inner_iters = 16;
+    if (c.inner_iters <= 0) c.inner_iters = 12;
     if (c.inner_tol <= 0) c.inner_tol = 1e-2;
     if (c.s_min <= 0) c.s_min = 3;
     if (c.probe_every <= 0) c.probe_every = 16;

@@ -207,7 +207,7 @@ void upload_topology(Group& g, Allocs& a, hipStream_t s) {
 void build_group_topology(ebe_batch* b, const MeshIn& m, Topology& T, int ct) {
     std::string e = build_topology(T, m.n_nodes, m.coords.data(), m.n_elems, m.conn.data(), m.elem_mat.data(),
                                    m.n_mat, m.mat.data(), m.fixed.data(), m.has_regions ? m.regions.data() : nullptr,
-                                   b->cfg.region_nodes, kMaxPatchElems / ct);
+                                   b->cfg.region_nodes, kMaxPatchElems / ct, PatchLds(), b->cfg.region_merge);
     if (!e.empty()) throw BErr{EBE_E_INVALID_ARG, e};
 }
 

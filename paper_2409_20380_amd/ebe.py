@@ -444,12 +444,13 @@ class Batch:
     or more meshes, advanced one time step together."""
 
     def __init__(self, dt, rayleigh_alpha=0.0, rayleigh_beta=0.0, tol=1e-8, s=16, predictor=PRED_SNAPSHOT,
-                 max_iter=10000, drop_tol=1e-6, region_nodes=512, s_min=0, fixed_window=False, stream=None):
+                 max_iter=10000, drop_tol=1e-6, region_nodes=512, s_min=0, fixed_window=False, region_merge=0,
+                 stream=None):
         import torch
         L = lib()
         cfg = Config(dt=dt, rayleigh_alpha=rayleigh_alpha, rayleigh_beta=rayleigh_beta, tol=tol, drop_tol=drop_tol,
                      max_iter=max_iter, s=s, predictor=predictor, region_nodes=region_nodes, s_min=s_min,
-                     fixed_window=int(bool(fixed_window)))
+                     fixed_window=int(bool(fixed_window)), region_merge=region_merge)
         self.cfg = cfg
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()

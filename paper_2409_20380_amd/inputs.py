@@ -317,3 +317,4 @@ WORKLOADS = {"plain": PLAIN, "large": LARGE, "small": SMALL}
 # batched ensemble: (cells, cases) per mesh; cases take seeds 1..64 in order
 ENSEMBLE = (((16, 16, 8), 20), ((32, 32, 16), 24), ((48, 48, 24), 20))
 ENSEMBLE_STEPS, ENSEMBLE_S = 500, 32
+ENSEMBLE_REGION_MERGE = 27   # as the single-mesh workloads: runs of 27 blocks of 8^3 lattice nodes

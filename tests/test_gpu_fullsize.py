@@ -51,8 +51,12 @@ def test_headline_mesh_rhs_and_steps_match_oracle(oracle_lib):
     say("full size: build", wl.cells, "(oracle assembly ~30 s)")
     c = _build(wl, oracle_lib)
     m, fx = c["model"], c["fx"]
-    sol = ebe.Solver(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol)
+    # the bench's configuration: the 8^3-lattice-node blocks merged 27 at a time into the predictor's
+    # regions; the oracle's map takes the merged partition the library reports
+    sol = ebe.Solver(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol, region_merge=wl.region_merge)
     sol.assemble(c["mesh"].coords, c["mesh"].conn, c["em"], c["mat"], fx, c["regions"])
+    c["regions"], n_reg = sol.regions()
+    say("full size:", n_reg, "predictor regions")
     # right-hand side of a seeded state over the whole vector (dual-operand element pass)
     say("full size: rhs")
     free = fx.ravel() == 0
@@ -109,8 +113,16 @@ def test_largest_ensemble_mesh_cases_match_oracle(oracle_lib):
     wl = inputs.Workload("ens_large", cells=cells, nt=nt, s=inputs.ENSEMBLE_S)
     say("full-size ensemble group", cells, "cases", r, "steps", nt)
     c = _build(wl, oracle_lib)
-    b = ebe.Batch(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol)
+    # the ensemble bench's merged predictor regions; the batch builds the same partition as a
+    # single-case handle on the same mesh, which reports it for the oracle
+    merge = inputs.ENSEMBLE_REGION_MERGE
+    b = ebe.Batch(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol, region_merge=merge)
     b.add_mesh(c["mesh"].coords, c["mesh"].conn, c["em"], c["mat"], c["fx"], c["regions"], r)
+    probe_sol = ebe.Solver(wl.dt, c["aR"], c["bR"], s=wl.s, tol=wl.tol, region_merge=merge)
+    probe_sol.assemble(c["mesh"].coords, c["mesh"].conn, c["em"], c["mat"], c["fx"], c["regions"])
+    c["regions"], n_reg = probe_sol.regions()
+    probe_sol.close()
+    say("predictor regions", n_reg)
     b.assemble(tune=True)
     say("tuned", b.group_info(0))
     waves = [inputs.base_wave(1 + k, nt, wl.dt) for k in range(r)]

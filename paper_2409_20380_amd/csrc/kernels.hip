@@ -1307,12 +1307,14 @@ __global__ __launch_bounds__(256) void k_gram(ColPtrs W, int s_eff, const int32_
         out[1024 + threadIdx.x] = (hq[0][threadIdx.x] + hq[1][threadIdx.x]) + (hq[2][threadIdx.x] + hq[3][threadIdx.x]);
 }
 
-// Least-squares coefficients of one region (one 64-lane workgroup): the
-// region's Gram is the sum of its chunks' partial Grams, in chunk order; with
-// column scaling d_j = sqrt(G_jj), Cholesky of the scaled Gram taken column by
-// column in time order; a column whose remaining (orthogonal) part is below
-// drop * its norm is dropped, which reproduces the column selection of
-// modified Gram-Schmidt in that order.  Then R^T y = h, R a = y, coef = a / d.
+// Least-squares coefficients of one region (one 256-thread workgroup): the
+// region's Gram is the sum of its chunks' partial Grams, taken by 8 streams
+// (chunk c to stream (c - first) mod 8, in chunk order within a stream) and
+// combined in a fixed tree; with column scaling d_j = sqrt(G_jj), Cholesky of
+// the scaled Gram taken column by column in time order; a column whose
+// remaining (orthogonal) part is below drop * its norm is dropped, which
+// reproduces the column selection of modified Gram-Schmidt in that order.
+// Then R^T y = h, R a = y, coef = a / d.
 // Broadcast of lane l's value (l a compile-time constant in the unrolled loops below).
 __device__ __forceinline__ double lane_value(double v, int l) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -1320,31 +1322,54 @@ __device__ __forceinline__ double lane_value(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
-// One wavefront per region; lane = column index throughout.  Each lane keeps
-// its column of the (scaled) Gram matrix in registers; row values of other
-// columns come by readlane at unrolled, compile-time lane indices, so the
-// factorisation has no LDS round trip and no barrier per pivot.  The column
-// oriented Cholesky with pivot drop, the forward and the back substitution
-// perform the same operations in the same order as a row-by-row
-// implementation (the back substitution reads R^T from one LDS copy).
-__global__ __launch_bounds__(64) void k_ls_solve(const double* gh, const int32_t* region_chunk, int s, double drop,
-                                                 double* coef, const int32_t* region_case, const int32_t* case_lo,
-                                                 int lo_all) {
+// The sum over the chunks: the half-waves of the four waves each read every
+// 8th chunk (a region of 14,000 nodes has 28 chunks: the serial sum of one
+// wave waited for 28 round trips to memory).  Then every wave runs the same
+// factorisation on the same sums, lane = column index; only wave 0 writes.
+// Each lane keeps its column of the (scaled) Gram matrix in registers; row
+// values of other columns come by readlane at unrolled, compile-time lane
+// indices, so the factorisation has no LDS round trip and no barrier per
+// pivot.  The column oriented Cholesky with pivot drop, the forward and the
+// back substitution perform the same operations in the same order as a
+// row-by-row implementation (the back substitution reads R^T from one LDS copy).
+__global__ __launch_bounds__(256) void k_ls_solve(const double* gh, const int32_t* region_chunk, int s, double drop,
+                                                  double* coef, const int32_t* region_case, const int32_t* case_lo,
+                                                  int lo_all) {
     __shared__ double R[32][33];
-    const int r = blockIdx.x, lane = threadIdx.x;
+    __shared__ double part[4][34][32];   // per wave: G[i][column] (i < 32), h[column], G[column][column]
+    const int r = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int cl = lane & 31, stream = 2 * wave + (lane >> 5);
     // columns before lo are left out: zero in the Gram, never kept, zero coefficients
     const int lo = lo_all + (case_lo ? case_lo[region_case[r]] : 0);
-    const bool col = lane >= lo && lane < s;
-    double g[32], y = 0.0, gll = 0.0;   // g[i] = G[i][lane]; gll = G[lane][lane], summed in the same order
+    const bool ccol = cl >= lo && cl < s;
+    double g[32], y = 0.0, gll = 0.0;   // g[i] = G[i][column]; gll = G[column][column]
 #pragma unroll
     for (int i = 0; i < 32; ++i) g[i] = 0.0;
-    for (int c = region_chunk[r]; c < region_chunk[r + 1]; ++c) {
+    for (int c = region_chunk[r] + stream; c < region_chunk[r + 1]; c += 8) {
         const double* in = gh + (int64_t)c * kGhStride;
 #pragma unroll
-        for (int i = 0; i < 32; ++i) g[i] += (col && i < s) ? in[i * 32 + lane] : 0.0;
-        y += col ? in[1024 + lane] : 0.0;
-        gll += col ? in[lane * 32 + lane] : 0.0;
+        for (int i = 0; i < 32; ++i) g[i] += (ccol && i < s) ? in[i * 32 + cl] : 0.0;
+        y += ccol ? in[1024 + cl] : 0.0;
+        gll += ccol ? in[cl * 32 + cl] : 0.0;
     }
+    // streams 2w and 2w + 1 (the two half-waves), then the four waves: ((w0 + w1) + (w2 + w3))
+#pragma unroll
+    for (int i = 0; i < 32; ++i) g[i] += __shfl_down(g[i], 32, 64);
+    y += __shfl_down(y, 32, 64);
+    gll += __shfl_down(gll, 32, 64);
+    if (lane < 32) {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) part[wave][i][cl] = g[i];
+        part[wave][32][cl] = y;
+        part[wave][33][cl] = gll;
+    }
+    __syncthreads();
+    const bool col = lane < 32 && ccol;   // lanes 32..63 hold no column
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        g[i] = col ? (part[0][i][cl] + part[1][i][cl]) + (part[2][i][cl] + part[3][i][cl]) : 0.0;
+    y = col ? (part[0][32][cl] + part[1][32][cl]) + (part[2][32][cl] + part[3][32][cl]) : 0.0;
+    gll = col ? (part[0][33][cl] + part[1][33][cl]) + (part[2][33][cl] + part[3][33][cl]) : 0.0;
     const double dl = col ? sqrt(gll) : 0.0;
     // scaling by the column norms: G_il / (d_i d_l), h_l / d_l
 #pragma unroll
@@ -1383,7 +1408,7 @@ __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, const int32_t
     }
 #pragma unroll
     for (int i = 0; i < 32; ++i)
-        if (lane < 32) R[i][lane] = g[i];   // R[i][l] from lane l
+        if (wave == 0 && lane < 32) R[i][lane] = g[i];   // R[i][l] from lane l
     __syncthreads();
 #pragma unroll
     for (int j = 31; j >= 0; --j) {    // R a = y
@@ -1393,7 +1418,7 @@ __global__ __launch_bounds__(64) void k_ls_solve(const double* gh, const int32_t
             if (lane < j) y -= R[lane][j] * yj;
         }
     }
-    if (lane < 32) coef[32 * (int64_t)r + lane] = (col && ((keep >> lane) & 1)) ? y / dl : 0.0;
+    if (wave == 0 && lane < 32) coef[32 * (int64_t)r + lane] = (col && ((keep >> lane) & 1)) ? y / dl : 0.0;
 }
 
 void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C, double drop, double* gh,
@@ -1402,7 +1427,7 @@ void launch_gram_solve(hipStream_t s, const ColPtrs& W, int s_eff, const DevChun
         hipLaunchKernelGGL(k_gram<1>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
     else
         hipLaunchKernelGGL(k_gram<2>, dim3(C.n_chunks), dim3(256), 0, s, W, s_eff, C.start, gh);
-    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(64), 0, s, gh, C.first, s_eff, drop, coef, C.region_case,
+    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(256), 0, s, gh, C.first, s_eff, drop, coef, C.region_case,
                        case_lo, 0);
 }
 
@@ -1415,7 +1440,7 @@ void launch_gram(hipStream_t s, const ColPtrs& W, int s_eff, const DevChunks& C,
 
 void launch_ls_solve(hipStream_t s, int s_eff, const DevChunks& C, double drop, const double* gh, double* coef,
                      int lo) {
-    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(64), 0, s, gh, C.first, s_eff, drop, coef,
+    hipLaunchKernelGGL(k_ls_solve, dim3(C.n_regions), dim3(256), 0, s, gh, C.first, s_eff, drop, coef,
                        (const int32_t*)nullptr, (const int32_t*)nullptr, lo);
 }
 
@@ -1425,7 +1450,9 @@ void launch_ls_solve(hipStream_t s, int s_eff, const DevChunks& C, double drop, 
 __global__ __launch_bounds__(256) void k_pred_apply(ColPtrs W, int s_eff, const int32_t* chunk_start,
                                                     const int32_t* chunk_region, const double* coef,
                                                     const double* dab, double* x) {
-    const int c = blockIdx.x;
+    // chunks in the reverse of the Gram pass's order: the columns that pass
+    // read last are the ones still in the memory-side cache
+    const int c = gridDim.x - 1 - blockIdx.x;
     const int64_t d0 = 3 * (int64_t)chunk_start[c], d1 = 3 * (int64_t)chunk_start[c + 1];
     const double* a = coef + 32 * (int64_t)chunk_region[c];
     for (int64_t i = d0 + threadIdx.x; i < d1; i += 256) {

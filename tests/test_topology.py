@@ -250,19 +250,26 @@ def _morton_codes(p, lo, hi):
     return out
 
 
-@pytest.mark.parametrize("merge", [2, 3, 8])
-def test_region_merge(probe, merge):
-    """Merged predictor regions: the given regions, ordered by the Morton code of their centroids, merged
-    `merge` at a time; each merged region is one contiguous range of the internal order; the patches are
-    as compact as without merging (the given regions still order the nodes)."""
+@pytest.mark.parametrize("merge,own", [(2, False), (3, False), (8, False), (4, True)])
+def test_region_merge(probe, merge, own):
+    """Merged predictor regions: the given regions (or, with no region map, the library's own regions of
+    region_nodes nodes), ordered by the Morton code of their centroids, merged `merge` at a time; each
+    merged region is one contiguous range of the internal order; the patches are as compact as without
+    merging (the given regions still order the nodes)."""
     wl = inputs.Workload("box8x8x8_rb4", cells=(8, 8, 8), nt=1, s=1, region_block=4)
     mesh, em, mat, fx, given, _ = wl.build()
     a = lambda x, t: np.ascontiguousarray(x, dtype=t)
     P = lambda x: x.ctypes.data_as(C.c_void_p)
     xyz, conn = a(mesh.coords, np.float64), a(mesh.conn, np.int32)
+    reg = None if own else P(a(given, np.int32))
     args = lambda m: (C.c_int64(mesh.n_nodes), P(xyz), C.c_int64(len(conn)), P(conn), P(a(em, np.int32)),
-                      C.c_int(len(mat)), P(a(mat, np.float64)), P(a(fx, np.uint8)), P(a(given, np.int32)),
-                      C.c_int(512), C.c_int(256), *(C.c_int64(v) for v in (120, 24, 48, 81920)), C.c_int(m))
+                      C.c_int(len(mat)), P(a(mat, np.float64)), P(a(fx, np.uint8)), reg,
+                      C.c_int(128), C.c_int(256), *(C.c_int64(v) for v in (120, 24, 48, 81920)), C.c_int(m))
+    if own:   # the library's own regions: Morton chunks of 128 nodes, as built without merging
+        assert probe.probe_build_merge(*args(1)) == 0
+        given = np.zeros(mesh.n_nodes, np.int32)
+        rs0 = np.zeros(mesh.n_nodes + 2, np.int32)
+        probe.probe_regions(P(given), P(rs0), C.c_int32(len(rs0)))
     R = int(given.max()) + 1
     stats = {}
     for m in (1, merge):
@@ -270,6 +277,7 @@ def test_region_merge(probe, merge):
         ru = np.zeros(mesh.n_nodes, np.int32)
         rs = np.zeros(R + 2, np.int32)
         nr = probe.probe_regions(P(ru), P(rs), C.c_int32(R + 2))
+        assert nr <= R
         sz = np.zeros(7, np.int64)
         probe.probe_sizes(P(sz))
         i2u = np.zeros(mesh.n_nodes, np.int32)

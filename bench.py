@@ -288,6 +288,7 @@ def main():
                    "s_min": ecfg.s_min, "input": ("base acceleration" if args.input == "base" else
                                                   "surface impulses (284 points)"),
                    "region_nodes": wl_run.region_block ** 3 * max(1, merge),
+                   "region_merge": max(1, merge),
                    "drop_tol": drop,
                    "timed_steps": f"{args.warmup + 1}-{nt}",
                    "refine": ("block-Jacobi PCG, FP64" if args.precision == "fp64" else

@@ -141,6 +141,9 @@ def main():
     ap.add_argument("--region-merge", type=int, default=-1,
                     help="given regions merged per predictor region, in Morton order of their centroids "
                          "(-1: the workload's, 1 = none)")
+    ap.add_argument("--energy", action="store_true",
+                    help="plain/large: GPU energy over the timed steps from the amd-smi energy counter "
+                         "(timed region of 4 s or more)")
     ap.add_argument("--workload", choices=["plain", "large", "learned", "ensemble"], default="plain")
     ap.add_argument("--no-graph", action="store_true", help="ensemble: enqueue PCG trips without hipGraph")
     ap.add_argument("--no-tune", action="store_true", help="ensemble: default case tiles instead of the autotuner")
@@ -238,7 +241,9 @@ def main():
 
     sol.set_kernel_timing(args.timing_every)
     iters, res, inner, res0, s_eff, kept = [], [], [], [], [], []
+    energy = gpu_energy_reader() if args.energy else None
     torch.cuda.synchronize()
+    e0 = energy() if energy else None
     t0 = time.perf_counter()
     for it in range(args.warmup + 1, nt + 1):
         f, g = forcing(it)
@@ -253,6 +258,7 @@ def main():
             raise RuntimeError(f"step {it} did not converge")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    e1 = energy() if energy else None
     n_timed, ebe_ms = sol.kernel_time()
     log(f"timed {args.steps} steps in {elapsed:.3f} s; mean iters {np.mean(iters):.1f}; "
         f"matvec {ebe_ms * 1e3:.1f} us over {n_timed} timed launches")
@@ -309,6 +315,12 @@ def main():
                      "traffic_note": "HBM bytes per launch from FETCH_SIZE/WRITE_SIZE, scaled by a 1 GiB copy",
                      "bytes_per_launch": launch_bytes, "mean_launch_ms": ebe_ms, "timed_launches": n_timed},
     }
+    if args.energy:
+        # the accumulator advances in coarse updates: only a timed region of several seconds gives a figure
+        out["energy"] = None if e0 is None or e1 is None or elapsed < 4.0 else {
+            "joules_per_step": (e1 - e0) / args.steps, "mean_power_w": (e1 - e0) / elapsed,
+            "joules_per_mdof_step": (e1 - e0) / args.steps / (dof * 1e-6),
+            "source": "amd-smi energy accumulator of this GPU, read before and after the timed steps"}
     pred_regions, _ = sol.regions()   # the predictor's regions (merged ones when region_merge > 1)
     sol.close()
     if not args.no_cpu_baseline and args.workload == "plain" and args.input == "base" and args.predictor == 2 \
@@ -550,6 +562,36 @@ def read_kv(path: str) -> dict:
                 k, v = line.split("=", 1)
                 out[k.strip()] = v.strip()
     return out
+
+
+def gpu_energy_reader():
+    """A function returning the cumulative energy (J) of this process's GPU from the
+    amd-smi library's energy accumulator, or None where it is not available."""
+    try:
+        import amdsmi
+        import torch
+        amdsmi.amdsmi_init()
+        handles = amdsmi.amdsmi_get_processor_handles()
+        prop = torch.cuda.get_device_properties(0)
+        bdf = None
+        if all(hasattr(prop, a) for a in ("pci_domain_id", "pci_bus_id", "pci_device_id")):
+            bdf = f"{prop.pci_domain_id:04x}:{prop.pci_bus_id:02x}:{prop.pci_device_id:02x}.0"
+        pick = [h for h in handles if bdf and amdsmi.amdsmi_get_gpu_device_bdf(h).lower() == bdf]
+        if not pick and len(handles) == 1:
+            pick = handles
+        if not pick:
+            return None
+        h = pick[0]
+
+        def read():
+            e = amdsmi.amdsmi_get_energy_count(h)
+            return e["energy_accumulator"] * e["counter_resolution"] * 1e-6
+
+        read()
+        return read
+    except Exception as exc:   # no library, no permission, no such device: no energy figure
+        log(f"energy counter not available: {exc}")
+        return None
 
 
 def kernel_source_sha() -> str:
